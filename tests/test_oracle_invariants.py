@@ -1,0 +1,110 @@
+"""Invariants the oracle's full step must satisfy (Sec. II-III).
+
+* a uniform equilibrium state is a fixed point;
+* on a periodic grid mass, momentum and energy (rows 1..4 of M) are conserved
+  to round-off (the collision leaves them untouched, the fluxes telescope);
+* a 90 degree rotation and a mirror of the initial state rotate / mirror the
+  solution (catches any x/y or index mix-up in the split fluxes);
+* an nx x 1 run equals every row of an nx x 8 run with y-uniform data;
+* outflow and equilibrium boundaries do not disturb nodes the waves have not
+  reached (domain of dependence of the explicit stencil).
+"""
+import numpy as np
+import pytest
+
+from paper_1305_4736_amd import workloads as W
+
+
+def test_uniform_state_is_fixed_point(orc):
+    c = W.random_smooth(12, 10, seed=3, nsteps=20)
+    p = c["params"]
+    f0 = orc.init(p, 1.3, 0.11, -0.07, 0.9)
+    f1 = orc.advance(p, f0, 20)
+    assert np.abs(f1 - f0).max() <= 1e-14 * np.abs(f0).max() * 20
+
+
+def _totals(orc, p, f):
+    v, M, Mi, A = orc.constants(p["eta0"])
+    m = np.einsum("ki,iyx->kyx", M[:4], f)
+    return m.reshape(4, -1).sum(axis=1)
+
+
+@pytest.mark.parametrize("limiter", ["mc", "minmod", "lw", "upwind"])
+def test_conservation_periodic(orc, limiter):
+    c = W.random_smooth(16, 12, seed=11, limiter=limiter, jumps=True)
+    p = c["params"]
+    f = orc.init(p, c["rho"], c["ux"], c["uy"], c["T"])
+    t0 = _totals(orc, p, f)
+    f = orc.advance(p, f, 60)
+    t1 = _totals(orc, p, f)
+    scale = np.array([abs(t0[0]), abs(t0[0]), abs(t0[0]), abs(t0[3])])
+    assert np.all(np.abs(t1 - t0) <= 1e-13 * scale), (t0, t1)
+    # the state did change (the test is not vacuous)
+    assert np.abs(f - orc.init(p, c["rho"], c["ux"], c["uy"], c["T"])).max() > 1e-3
+
+
+def _rot_field(a):
+    """new[y', x'] = old[(-x') mod N, y'] : the field rotated by +90 degrees."""
+    n = a.shape[0]
+    yp, xp = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    return a[(-xp) % n, yp]
+
+
+def test_rotation_symmetry(orc):
+    n = 14
+    c = W.random_smooth(n, n, seed=5, jumps=True, nsteps=25)
+    p = c["params"]
+    r, ux, uy, T = c["rho"], c["ux"], c["uy"], c["T"]
+    fa = orc.run(p, r, ux, uy, T, 25)
+    ra, uxa, uya, Ta = orc.macros(p, fa)
+    # rotate the initial state: scalars move, velocity vectors turn by +90 degrees
+    fb = orc.run(p, _rot_field(r), -_rot_field(uy), _rot_field(ux), _rot_field(T), 25)
+    rb, uxb, uyb, Tb = orc.macros(p, fb)
+    assert np.abs(rb - _rot_field(ra)).max() < 1e-12
+    assert np.abs(Tb - _rot_field(Ta)).max() < 1e-12
+    assert np.abs(uxb - (-_rot_field(uya))).max() < 1e-12
+    assert np.abs(uyb - _rot_field(uxa)).max() < 1e-12
+
+
+def test_mirror_symmetry(orc):
+    n = 12
+    c = W.random_smooth(n, 9, seed=8, jumps=True, nsteps=25)
+    p = c["params"]
+    mir = lambda a: a[:, (-np.arange(n)) % n]
+    fa = orc.run(p, c["rho"], c["ux"], c["uy"], c["T"], 25)
+    ra, uxa, uya, Ta = orc.macros(p, fa)
+    fb = orc.run(p, mir(c["rho"]), -mir(c["ux"]), mir(c["uy"]), mir(c["T"]), 25)
+    rb, uxb, uyb, Tb = orc.macros(p, fb)
+    assert np.abs(rb - mir(ra)).max() < 1e-12
+    assert np.abs(uxb + mir(uxa)).max() < 1e-12
+    assert np.abs(uyb - mir(uya)).max() < 1e-12
+    assert np.abs(Tb - mir(Ta)).max() < 1e-12
+
+
+def test_single_row_equals_uniform_rows(orc):
+    c1 = W.sod(nx=80)
+    c8 = W.sod(nx=80, ny=8)
+    n = 150
+    f1 = orc.run(c1["params"], c1["rho"], c1["ux"], c1["uy"], c1["T"], n)
+    f8 = orc.run(c8["params"], c8["rho"], c8["ux"], c8["uy"], c8["T"], n)
+    for y in range(8):
+        assert np.abs(f8[:, y, :] - f1[:, 0, :]).max() < 1e-13
+
+
+def test_boundaries_do_not_act_ahead_of_waves(orc):
+    """Equilibrium / outflow / periodic x-boundaries only differ near the edge:
+    after n steps the stencil (reach 2 nodes per step) has carried the
+    difference at most 2n nodes inward."""
+    c = W.riemann_1d((1.0, 0.2, 1.0), (0.5, 0.2, 0.6), 1.4, 120, nsteps=0)
+    n = 20
+    outs = []
+    for kinds in (("equilibrium", "equilibrium"), ("outflow", "outflow"), ("periodic", "periodic")):
+        p = dict(c["params"])
+        p["bc"] = [dict(c["params"]["bc"][0], kind=kinds[0]), dict(c["params"]["bc"][1], kind=kinds[1]),
+                   c["params"]["bc"][2], c["params"]["bc"][3]]
+        outs.append(orc.run(p, c["rho"], c["ux"], c["uy"], c["T"], n))
+    inner = slice(2 * n + 1, 120 - 2 * n - 1)
+    for o in outs[1:]:
+        assert np.abs(o[:, :, inner] - outs[0][:, :, inner]).max() == 0.0
+    # and the periodic wrap does differ near the edges
+    assert np.abs(outs[2] - outs[0]).max() > 1e-8
