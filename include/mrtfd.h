@@ -1,0 +1,155 @@
+/*
+ * mrtfd.h -- C ABI of the MI355X (gfx950) implementation of the per-time-step
+ * update of the two-dimensional MRT finite-difference lattice-Boltzmann model
+ * of Chen, Xu, Zhang and Wang, "Two dimensional MRT LB model for
+ * compressible and incompressible flows" (arXiv:1305.4736).
+ *
+ * The method (what one step computes, Sec. III update equation):
+ *   f_i^{n+1} = f_i^n - nu_ix [F_{i,J+1/2} - F_{i,J-1/2}]_x
+ *                     - nu_iy [F_{i,J+1/2} - F_{i,J-1/2}]_y
+ *                     - dt M^-1 [ S (fhat - fhat^eq) + C ]
+ * on the 16-velocity Kataoka-Tsutahara set (Sec. II, Fig. 1), with fhat = M f
+ * (Appendix, m_1..m_16), equilibria of the non-conserved moments from the
+ * seven moment relations (Appendix), the energy-flux correction C_8, C_9 of
+ * moments 8 and 9 (Sec. II), face fluxes limited by psi(theta) (Sec. III,
+ * flux, limiter and smoothness equations) and every term taken at level n.
+ *
+ * Conventions shared by every entry point
+ *  - Velocity order: four groups of four, |v| = 1, 6, 2, 3; inside a group
+ *    counter-clockwise, axis groups starting at +x, diagonal groups at (+,+).
+ *  - Fields are row-major (ny, nx) arrays, x fastest; f and the
+ *    non-equilibrium planes are (16, ny, nx).  All exchanged values are
+ *    double precision, whatever the storage precision.
+ *  - R = 1 (P = rho T); gamma = (b + 2) / b; eta0 is the extra-DOF
+ *    parameter of the |v| = 1 group (5/2 in the paper, Appendix).
+ *  - on_device = 1: pointers are device pointers (e.g. torch tensors' data
+ *    pointers) valid on the handle's stream; on_device = 0: host pointers,
+ *    the call then synchronises the stream before returning.
+ *  - Every call returns MRTFD_OK or a negative status; no exception crosses
+ *    the ABI.  mrtfd_last_error() gives the message of the last failure on
+ *    the calling thread.
+ *  - A handle is not thread-safe; separate handles are independent.  The
+ *    caller owns every buffer it passes; the library owns all device state of
+ *    a handle and frees it in mrtfd_destroy().
+ */
+#ifndef MRTFD_H
+#define MRTFD_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MRTFD_OK 0
+#define MRTFD_EINVAL (-1)     /* invalid argument or unsupported combination */
+#define MRTFD_ENOMEM (-2)     /* device allocation failed */
+#define MRTFD_EDEVICE (-3)    /* HIP runtime error (message has the HIP error) */
+#define MRTFD_ENONFINITE (-4) /* a node had rho <= 0, T <= 0 or NaN since the last check */
+#define MRTFD_ESTATE (-5)     /* call out of order (e.g. step before init) */
+
+/* Boundary kinds (Sec. IV-A: f = M^-1 fhat^eq of a fixed state; Sec. IV-C:
+ * periodic and non-equilibrium-extrapolation walls; Sec. V: inflow, outflow). */
+enum {
+    MRTFD_BC_PERIODIC = 0,    /* must be used on both sides of an axis */
+    MRTFD_BC_EQUILIBRIUM = 1, /* two ghost layers fixed at f^eq(rho, u, T); also inflow */
+    MRTFD_BC_OUTFLOW = 2,     /* ghosts copy the last interior node (zero gradient) */
+    MRTFD_BC_WALL_NEE = 3     /* wall on the first/last grid line: f_w = f^eq(rho_w, u_w, T_w)
+                                 + (f_1 - f^eq_1), rho_w T_w = rho_1 T_1, ghosts continue the
+                                 line through f_1 and f_w; walls on one axis only */
+};
+
+/* Flux limiter psi(theta) (Sec. III): the paper's piecewise form (MC),
+ * minmod, Lax-Wendroff (psi = 1) and first-order upwind (psi = 0). */
+enum { MRTFD_LIM_MC = 0, MRTFD_LIM_MINMOD = 1, MRTFD_LIM_LW = 2, MRTFD_LIM_UPWIND = 3 };
+
+/* Storage precision: FP64 everywhere, or f stored and convected in FP32 with
+ * the conserved-moment sums, temperature, equilibria, collision and the
+ * M / M^-1 constants in FP64. */
+enum { MRTFD_FP64 = 0, MRTFD_FP32_STORAGE = 1 };
+
+typedef struct {
+    int kind;                /* MRTFD_BC_* */
+    double rho, ux, uy, T;   /* state used by EQUILIBRIUM; ux, uy, T by WALL_NEE */
+} mrtfd_bc;
+
+typedef struct {
+    int nx, ny;              /* grid nodes, wall nodes included; >= 1 */
+    double dx, dy, dt;       /* spacing and time step (> 0) */
+    double eta0;             /* 2.5 in the paper */
+    double s[16];            /* relaxation rates s_1..s_16 (s_1..s_4 have no effect) */
+    double b;                /* gamma = (b + 2) / b, > 0 */
+    int limiter;             /* MRTFD_LIM_* */
+    int precision;           /* MRTFD_FP64 or MRTFD_FP32_STORAGE */
+    int energy_flux_correction; /* 1: C_8, C_9 on (needs s_5 != 0); 0: off */
+    mrtfd_bc bc[4];          /* sides x-lo, x-hi, y-lo, y-hi */
+} mrtfd_params;
+
+typedef struct mrtfd_s* mrtfd_t;
+
+/* Validate the parameters, allocate the two ping-pong state buffers (16
+ * planes each, two ghost layers, rows padded to 128-byte lines) and bind the
+ * handle to `hip_stream` (a hipStream_t; NULL = the null stream).  Rejects:
+ * non-positive sizes or steps, unpaired periodic sides, walls on both axes,
+ * grids too small for their walls, 6 dt (1/dx + 1/dy) > 2 (the unsplit
+ * Courant bound on the fastest |v| = 6 velocities is checked per axis:
+ * 6 dt / dx <= 1 and 6 dt / dy <= 1), dt * max(s_5..s_16) >= 2. */
+int mrtfd_create(const mrtfd_params* p, void* hip_stream, mrtfd_t* out);
+
+/* Device bytes a handle with these parameters will hold (state buffers and
+ * scratch), for admission control.  Host-only. */
+int mrtfd_footprint(const mrtfd_params* p, size_t* bytes);
+
+/* f = M^-1 fhat^eq(rho, u, T) at every node (Sec. IV-A), then the boundary
+ * fill (ghosts, wall nodes).  Each input is an (ny, nx) array. */
+int mrtfd_init(mrtfd_t h, const double* rho, const double* ux, const double* uy,
+               const double* T, int on_device);
+
+/* Advance by nsteps explicit stages; one fused kernel launch per step
+ * (moments, equilibria, correction, collision, limited fluxes, update and
+ * boundary fill).  Asynchronous on the handle's stream. */
+int mrtfd_step(mrtfd_t h, long nsteps);
+
+/* As mrtfd_step, and report the elapsed device time of those launches in
+ * milliseconds, measured with HIP events on the handle's stream
+ * (synchronises). */
+int mrtfd_step_timed(mrtfd_t h, long nsteps, double* elapsed_ms);
+
+/* rho, u_x, u_y, T (Sec. II: P = rho T, e = b rho T + rho u^2) at every node;
+ * any output may be NULL. */
+int mrtfd_macros(mrtfd_t h, double* rho, double* ux, double* uy, double* T, int on_device);
+
+/* Non-equilibrium moments (Sec. V): star = 0 gives Delta = M (f - f^eq),
+ * star = 1 gives Delta* = M*(u) (f - f^eq), M* being M with v replaced by
+ * v - u (Appendix).  Output: (16, ny, nx). */
+int mrtfd_noneq(mrtfd_t h, int star, double* delta, int on_device);
+
+/* Checkpoint: copy the interior distribution out / in, (16, ny, nx) doubles
+ * (FP32 storage converts exactly on the way out, rounds on the way in).
+ * mrtfd_set_f refills ghosts and wall nodes. */
+int mrtfd_get_f(mrtfd_t h, double* f, int on_device);
+int mrtfd_set_f(mrtfd_t h, const double* f, int on_device);
+
+/* Wait for the handle's stream; returns MRTFD_ENONFINITE (and clears the
+ * flag) if any updated node saw rho <= 0, T <= 0 or NaN since the last
+ * check. */
+int mrtfd_sync(mrtfd_t h);
+
+/* Steps taken since mrtfd_init / mrtfd_set_f. */
+long mrtfd_steps_done(mrtfd_t h);
+
+int mrtfd_destroy(mrtfd_t h);
+
+/* Message of the last failure on this thread ("" if none).  The string is
+ * owned by the library and valid until the next call on this thread. */
+const char* mrtfd_last_error(void);
+
+/* Host-only: the dense 16x16 M and M^-1 (row-major) the kernels use in their
+ * factored form (per-group angular sums times small blocks), for checks. */
+int mrtfd_constants(double eta0, double* M, double* Minv);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MRTFD_H */

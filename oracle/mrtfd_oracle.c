@@ -370,8 +370,8 @@ static int params_ok(const orc_params* p)
     if ((p->bc_kind[2] == ORC_BC_PERIODIC) != (p->bc_kind[3] == ORC_BC_PERIODIC)) return 0;
     int wx = (p->bc_kind[0] == ORC_BC_WALL) + (p->bc_kind[1] == ORC_BC_WALL);
     int wy = (p->bc_kind[2] == ORC_BC_WALL) + (p->bc_kind[3] == ORC_BC_WALL);
-    if (p->nx < 1 + wx + (wx > 0)) return 0;
-    if (p->ny < 1 + wy + (wy > 0)) return 0;
+    if (wx && p->nx < wx + 1) return 0;   /* at least one fluid node between walls */
+    if (wy && p->ny < wy + 1) return 0;
     if (p->correction && p->s[4] == 0.0) return 0;
     return 1;
 }

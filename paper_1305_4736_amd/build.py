@@ -1,0 +1,42 @@
+"""Build the gfx950 shared library (the C ABI of include/mrtfd.h) in-tree.
+
+    python -m paper_1305_4736_amd.build
+
+compiles paper_1305_4736_amd/csrc/*.hip with hipcc for gfx950 into
+paper_1305_4736_amd/libmrtfd.so.  Packed FP32 instructions are disabled for
+the device code (``-Xclang -target-feature -Xclang -packed-fp32-ops``).
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+SRC = os.path.join(HERE, "csrc", "mrtfd.hip")
+LIB = os.path.join(HERE, "libmrtfd.so")
+HEADERS = [os.path.join(HERE, "csrc", n) for n in ("mrtfd_device.h", "mrtfd_consts.h")] + [
+    os.path.join(ROOT, "include", "mrtfd.h")]
+
+ARCH = os.environ.get("MRTFD_ARCH", "gfx950")
+FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}",
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-Wall", "-Wno-unused-function"]
+
+
+def build(verbose: bool = False) -> str:
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    tmp = LIB + ".tmp%d" % os.getpid()
+    cmd = [hipcc, *FLAGS, "-o", tmp, SRC]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose=True)
+    print("built", LIB)
+    sys.exit(0)

@@ -1,0 +1,288 @@
+// mrtfd_device.h -- device-side arithmetic of the D2V16 MRT-FD step for gfx950.
+//
+// Velocity i = 4 g + k (group g, k counter-clockwise).  Per group the four
+// populations are reduced to the angular sums
+//     S = sum f,  X = sum sgn(v_x) f,  Y = sum sgn(v_y) f,
+//     D = f_0 - f_1 + f_2 - f_3
+// and every row of M (Appendix, m_1..m_16) is a short combination of one kind
+// of sum over the four groups, so fhat = M f costs 4 x 8 adds plus five small
+// blocks (4x4, 4x4, 4x4, 2x2, 2x2) instead of a dense 16x16 product.  M^-1 is
+// the inverse blocks followed by the inverse angular sums.  The blocks are
+// built on the host (mrtfd_consts.h) and reach the kernels as arguments.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace mrtfd {
+
+constexpr int NQ = 16;
+constexpr int HALO = 2;     // ghost layers on every side
+
+// Component signs of the 16 velocities (Sec. II, Fig. 1).
+__host__ __device__ constexpr int sgx(int i)
+{
+    return (i < 8) ? ((i & 3) == 0 ? 1 : ((i & 3) == 2 ? -1 : 0))
+                   : (((i & 3) == 0 || (i & 3) == 3) ? 1 : -1);
+}
+__host__ __device__ constexpr int sgy(int i)
+{
+    return (i < 8) ? ((i & 3) == 1 ? 1 : ((i & 3) == 3 ? -1 : 0))
+                   : (((i & 3) == 0 || (i & 3) == 1) ? 1 : -1);
+}
+
+// Forward blocks: rows of M acting on the per-group sums.
+//   F0: (m_1, m_4, m_5, m_14) from S_g        FX: (m_2, m_8, m_10, m_12) from X_g
+//   FY: (m_3, m_9, m_11, m_13) from Y_g       FDa: (m_6, m_16) from D_0, D_1
+//   FDd: (m_7, m_15) from D_2, D_3
+// Inverse blocks (already carrying the inverse angular-sum factors 1/4, 1/2):
+//   I0[g][c]  : S'_g from column c of (m_1, m_4, m_5, m_14)
+//   IX[g][c], IY[g][c], IDa[g][c], IDd[g][c] likewise.
+struct Blocks {
+    double F0[4][4], FX[4][4], FY[4][4], FDa[2][2], FDd[2][2];
+    double I0[4][4], IX[4][4], IY[4][4], IDa[2][2], IDd[2][2];
+    double vmag[4];     // |v_x| (= |v_y|) of a moving component, per group
+};
+
+// Everything a step needs that is uniform over the grid.
+struct StepArgs {
+    Blocks B;
+    double s[NQ];
+    double b, inv_b, dt;
+    double nux[4], nuy[4];      // Courant numbers |v_ia| dt / d_a per group
+    double cx[4], cy[4];        // (1 - nu) / 2 per group and axis
+    double k8, k9;              // s_8 / s_5 - 1, s_9 / s_5 - 1 (0 when the correction is off)
+    double inv2dx, inv2dy;
+    double side[4][4];          // (rho, ux, uy, T) of each side: equilibrium ghosts, walls
+    int nx, ny;
+    long pitch;                 // elements per padded row
+    long plane;                 // elements per padded plane
+    long org;                   // element offset of node (0, 0) inside a plane
+    int x0, x1, y0, y1;         // evolved node range [x0, x1) x [y0, y1)
+    int bc[4];                  // kinds of x-lo, x-hi, y-lo, y-hi
+    int correction;
+    int* flag;                  // set to 1 when a node is unphysical
+};
+
+// ---------------------------------------------------------------------------
+// Angular sums of one group (axis groups 0, 1 and diagonal groups 2, 3).
+template <int G>
+__host__ __device__ __forceinline__ void group_sums(double f0, double f1, double f2, double f3, double& S,
+                                           double& X, double& Y, double& D)
+{
+    double p02 = f0 + f2, p13 = f1 + f3;
+    double m02 = f0 - f2, m13 = f1 - f3;
+    S = p02 + p13;
+    D = p02 - p13;
+    if (G < 2) {
+        X = m02;
+        Y = m13;
+    } else {
+        X = m02 - m13;
+        Y = m02 + m13;
+    }
+}
+
+// Inverse angular sums of one group from pre-scaled S', X', Y', D'.
+template <int G>
+__host__ __device__ __forceinline__ void group_unsums(double S, double X, double Y, double D, double* f)
+{
+    if (G < 2) {
+        double a = S + D, c = S - D;
+        f[0] = a + X;
+        f[2] = a - X;
+        f[1] = c + Y;
+        f[3] = c - Y;
+    } else {
+        double sp = S + D, sm = S - D;
+        double xp = X + Y, xm = X - Y;
+        f[0] = sp + xp;
+        f[1] = sm - xm;
+        f[2] = sp - xp;
+        f[3] = sm + xm;
+    }
+}
+
+struct Sums {
+    double S[4], X[4], Y[4], D[4];
+};
+
+__host__ __device__ __forceinline__ Sums all_sums(const double* f)
+{
+    Sums a;
+    group_sums<0>(f[0], f[1], f[2], f[3], a.S[0], a.X[0], a.Y[0], a.D[0]);
+    group_sums<1>(f[4], f[5], f[6], f[7], a.S[1], a.X[1], a.Y[1], a.D[1]);
+    group_sums<2>(f[8], f[9], f[10], f[11], a.S[2], a.X[2], a.Y[2], a.D[2]);
+    group_sums<3>(f[12], f[13], f[14], f[15], a.S[3], a.X[3], a.Y[3], a.D[3]);
+    return a;
+}
+
+__host__ __device__ __forceinline__ double dot4(const double* r, const double* v)
+{
+    return fma(r[0], v[0], fma(r[1], v[1], fma(r[2], v[2], r[3] * v[3])));
+}
+
+// fhat = M f from the angular sums (all 16 moments).
+__host__ __device__ __forceinline__ void moments(const Blocks& B, const Sums& a, double* m)
+{
+    m[0] = (a.S[0] + a.S[1]) + (a.S[2] + a.S[3]);
+    m[3] = dot4(B.F0[1], a.S);
+    m[4] = dot4(B.F0[2], a.S);
+    m[13] = dot4(B.F0[3], a.S);
+    m[1] = dot4(B.FX[0], a.X);
+    m[7] = dot4(B.FX[1], a.X);
+    m[9] = dot4(B.FX[2], a.X);
+    m[11] = dot4(B.FX[3], a.X);
+    m[2] = dot4(B.FY[0], a.Y);
+    m[8] = dot4(B.FY[1], a.Y);
+    m[10] = dot4(B.FY[2], a.Y);
+    m[12] = dot4(B.FY[3], a.Y);
+    m[5] = fma(B.FDa[0][0], a.D[0], B.FDa[0][1] * a.D[1]);
+    m[15] = fma(B.FDa[1][0], a.D[0], B.FDa[1][1] * a.D[1]);
+    m[6] = fma(B.FDd[0][0], a.D[2], B.FDd[0][1] * a.D[3]);
+    m[14] = fma(B.FDd[1][0], a.D[2], B.FDd[1][1] * a.D[3]);
+}
+
+// Equilibria of all 16 moments (Appendix, closing equations) from the
+// conserved ones, R = 1, written with u = j / rho.  Returns P; eq[0..3] are
+// the conserved moments themselves.
+__device__ __forceinline__ void equilibria(double rho, double ux, double uy, double P, double e,
+                                           double b, double* eq)
+{
+    double ux2 = ux * ux, uy2 = uy * uy, u2 = ux2 + uy2;
+    double ru2 = rho * u2;
+    double rdu = rho * (ux2 - uy2);
+    double T = P / rho;
+    eq[0] = rho;
+    eq[1] = rho * ux;
+    eq[2] = rho * uy;
+    eq[3] = e;
+    eq[4] = 2.0 * P + ru2;
+    eq[5] = rdu;
+    eq[6] = rho * ux * uy;
+    double e2p = e + 2.0 * P;
+    eq[7] = e2p * ux;
+    eq[8] = e2p * uy;
+    double q4 = 4.0 * P + ru2;
+    eq[9] = q4 * ux;
+    eq[10] = q4 * uy;
+    eq[11] = (2.0 * P + rdu) * ux;
+    eq[12] = (rdu - 2.0 * P) * uy;
+    eq[13] = 2.0 * (b + 2.0) * P * T + (6.0 + b) * P * u2 + ru2 * u2;
+    double hb = (b + 4.0) * P + ru2;
+    eq[14] = hb * ux * uy;
+    eq[15] = hb * (ux2 - uy2);
+}
+
+// v = M^-1 w for a moment vector w with w_1..w_4 = 0 (the collision residual
+// and the non-equilibrium part), using the pre-scaled inverse blocks.
+__host__ __device__ __forceinline__ void inverse_nc(const Blocks& B, const double* w, double* v)
+{
+    double S[4], X[4], Y[4], D[4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        S[g] = fma(B.I0[g][2], w[4], B.I0[g][3] * w[13]);
+        X[g] = fma(B.IX[g][1], w[7], fma(B.IX[g][2], w[9], B.IX[g][3] * w[11]));
+        Y[g] = fma(B.IY[g][1], w[8], fma(B.IY[g][2], w[10], B.IY[g][3] * w[12]));
+    }
+    D[0] = fma(B.IDa[0][0], w[5], B.IDa[0][1] * w[15]);
+    D[1] = fma(B.IDa[1][0], w[5], B.IDa[1][1] * w[15]);
+    D[2] = fma(B.IDd[0][0], w[6], B.IDd[0][1] * w[14]);
+    D[3] = fma(B.IDd[1][0], w[6], B.IDd[1][1] * w[14]);
+    group_unsums<0>(S[0], X[0], Y[0], D[0], v + 0);
+    group_unsums<1>(S[1], X[1], Y[1], D[1], v + 4);
+    group_unsums<2>(S[2], X[2], Y[2], D[2], v + 8);
+    group_unsums<3>(S[3], X[3], Y[3], D[3], v + 12);
+}
+
+// v = M^-1 w for a full moment vector.
+__host__ __device__ __forceinline__ void inverse_full(const Blocks& B, const double* w, double* v)
+{
+    double S[4], X[4], Y[4], D[4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        S[g] = fma(B.I0[g][0], w[0], fma(B.I0[g][1], w[3], fma(B.I0[g][2], w[4], B.I0[g][3] * w[13])));
+        X[g] = fma(B.IX[g][0], w[1], fma(B.IX[g][1], w[7], fma(B.IX[g][2], w[9], B.IX[g][3] * w[11])));
+        Y[g] = fma(B.IY[g][0], w[2], fma(B.IY[g][1], w[8], fma(B.IY[g][2], w[10], B.IY[g][3] * w[12])));
+    }
+    D[0] = fma(B.IDa[0][0], w[5], B.IDa[0][1] * w[15]);
+    D[1] = fma(B.IDa[1][0], w[5], B.IDa[1][1] * w[15]);
+    D[2] = fma(B.IDd[0][0], w[6], B.IDd[0][1] * w[14]);
+    D[3] = fma(B.IDd[1][0], w[6], B.IDd[1][1] * w[14]);
+    group_unsums<0>(S[0], X[0], Y[0], D[0], v + 0);
+    group_unsums<1>(S[1], X[1], Y[1], D[1], v + 4);
+    group_unsums<2>(S[2], X[2], Y[2], D[2], v + 8);
+    group_unsums<3>(S[3], X[3], Y[3], D[3], v + 12);
+}
+
+// f^eq in velocity space from primitive variables (rho, u, T).
+__device__ __forceinline__ void feq_velocity(const Blocks& B, double b, double rho, double ux,
+                                             double uy, double T, double* out)
+{
+    double P = rho * T;
+    double e = b * P + rho * (ux * ux + uy * uy);
+    double eq[NQ];
+    equilibria(rho, ux, uy, P, e, b, eq);
+    inverse_full(B, eq, out);
+}
+
+// rho, u, T of a node from its 16 populations.
+__device__ __forceinline__ void macro_of(const Blocks& B, double inv_b, const double* f,
+                                         double& rho, double& ux, double& uy, double& T)
+{
+    Sums a = all_sums(f);
+    rho = (a.S[0] + a.S[1]) + (a.S[2] + a.S[3]);
+    double jx = dot4(B.FX[0], a.X);
+    double jy = dot4(B.FY[0], a.Y);
+    double e = dot4(B.F0[1], a.S);
+    double ir = 1.0 / rho;
+    ux = jx * ir;
+    uy = jy * ir;
+    double P = (e - rho * (ux * ux + uy * uy)) * inv_b;
+    T = P * ir;
+}
+
+// Density and velocity only (neighbour ring of the correction).
+__device__ __forceinline__ void velocity_of(const Blocks& B, const double* f, double& ux, double& uy)
+{
+    Sums a = all_sums(f);
+    double rho = (a.S[0] + a.S[1]) + (a.S[2] + a.S[3]);
+    double ir = 1.0 / rho;
+    ux = dot4(B.FX[0], a.X) * ir;
+    uy = dot4(B.FY[0], a.Y) * ir;
+}
+
+// ---------------------------------------------------------------------------
+// Limited jump psi(theta) * dn with theta = up / dn, in division-free form
+// (equal to the printed piecewise limiter wherever theta is defined; zero
+// when the downstream jump vanishes).
+template <int LIM, typename R>
+__device__ __forceinline__ R limited(R up, R dn)
+{
+    if constexpr (LIM == 2) {           // Lax-Wendroff
+        return dn;
+    } else if constexpr (LIM == 3) {    // first-order upwind
+        return R(0);
+    } else {
+        R au = fabs(up), ad = fabs(dn);
+        bool same = (up > R(0)) ? (dn > R(0)) : ((up < R(0)) && (dn < R(0)));
+        R m;
+        if constexpr (LIM == 0)         // MC: min(2|a|, (|a| + |d|) / 2, 2|d|)
+            m = fmin(R(2) * fmin(au, ad), R(0.5) * (au + ad));
+        else                            // minmod
+            m = fmin(au, ad);
+        return same ? copysign(m, dn) : R(0);
+    }
+}
+
+// Convective increment of one population along one axis:
+//   -nu [ (f_J - f_{J-s}) + c (L(f_J - f_{J-s}, f_{J+s} - f_J) - L(f_{J-s} - f_{J-2s}, f_J - f_{J-s})) ]
+// with c = (1 - nu) / 2, s the sign of the velocity component.
+template <int LIM, typename R>
+__device__ __forceinline__ R conv1(R fm2, R fm1, R f0, R fp1, R nu, R c)
+{
+    R d0 = fm1 - fm2, d1 = f0 - fm1, d2 = fp1 - f0;
+    R l1 = limited<LIM>(d1, d2);
+    R l0 = limited<LIM>(d0, d1);
+    return -nu * fma(c, l1 - l0, d1);
+}
+
+}  // namespace mrtfd

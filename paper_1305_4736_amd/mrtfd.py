@@ -1,0 +1,238 @@
+"""Python binding of the C ABI in include/mrtfd.h (argument marshalling only).
+
+Every step of the method runs in the gfx950 kernels of ``libmrtfd.so``; this
+module converts a parameter dict (see ``workloads``) into ``mrtfd_params``,
+passes numpy arrays as host pointers or torch CUDA tensors as device
+pointers, and raises on any non-zero status.  There is no fallback: if the
+library has not been built the import fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmrtfd.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it with `python -m paper_1305_4736_amd.build` "
+        "(there is no CPU fallback)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+LIMITERS = {"mc": 0, "minmod": 1, "lw": 2, "upwind": 3}
+BC_KINDS = {"periodic": 0, "equilibrium": 1, "outflow": 2, "wall": 3}
+PRECISIONS = {"fp64": 0, "fp32": 1}
+
+OK, EINVAL, ENOMEM, EDEVICE, ENONFINITE, ESTATE = 0, -1, -2, -3, -4, -5
+
+
+class MRTFDError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class NonFiniteError(MRTFDError):
+    pass
+
+
+class _Bc(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("rho", ctypes.c_double), ("ux", ctypes.c_double),
+                ("uy", ctypes.c_double), ("T", ctypes.c_double)]
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int),
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dt", ctypes.c_double),
+                ("eta0", ctypes.c_double), ("s", ctypes.c_double * 16), ("b", ctypes.c_double),
+                ("limiter", ctypes.c_int), ("precision", ctypes.c_int),
+                ("energy_flux_correction", ctypes.c_int), ("bc", _Bc * 4)]
+
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_vp = ctypes.c_void_p
+_H = ctypes.c_void_p
+_lib.mrtfd_create.argtypes = [ctypes.POINTER(_Params), _vp, ctypes.POINTER(_H)]
+_lib.mrtfd_footprint.argtypes = [ctypes.POINTER(_Params), ctypes.POINTER(ctypes.c_size_t)]
+_lib.mrtfd_init.argtypes = [_H, _vp, _vp, _vp, _vp, ctypes.c_int]
+_lib.mrtfd_step.argtypes = [_H, ctypes.c_long]
+_lib.mrtfd_step_timed.argtypes = [_H, ctypes.c_long, _dp]
+_lib.mrtfd_macros.argtypes = [_H, _vp, _vp, _vp, _vp, ctypes.c_int]
+_lib.mrtfd_noneq.argtypes = [_H, ctypes.c_int, _vp, ctypes.c_int]
+_lib.mrtfd_get_f.argtypes = [_H, _vp, ctypes.c_int]
+_lib.mrtfd_set_f.argtypes = [_H, _vp, ctypes.c_int]
+_lib.mrtfd_sync.argtypes = [_H]
+_lib.mrtfd_steps_done.argtypes = [_H]
+_lib.mrtfd_steps_done.restype = ctypes.c_long
+_lib.mrtfd_destroy.argtypes = [_H]
+_lib.mrtfd_last_error.restype = ctypes.c_char_p
+_lib.mrtfd_constants.argtypes = [ctypes.c_double, _dp, _dp]
+
+
+def _check(rc: int):
+    if rc != OK:
+        msg = _lib.mrtfd_last_error().decode()
+        raise (NonFiniteError if rc == ENONFINITE else MRTFDError)(rc, msg)
+
+
+def c_params(p: dict) -> _Params:
+    c = _Params()
+    c.nx, c.ny = int(p["nx"]), int(p["ny"])
+    c.dx, c.dy, c.dt = float(p["dx"]), float(p["dy"]), float(p["dt"])
+    c.eta0 = float(p.get("eta0", 2.5))
+    for k in range(16):
+        c.s[k] = float(p["s"][k])
+    c.b = float(p["b"])
+    c.limiter = LIMITERS[p.get("limiter", "mc")]
+    c.precision = PRECISIONS[p.get("precision", "fp64")]
+    c.energy_flux_correction = 1 if p.get("correction", True) else 0
+    for side in range(4):
+        bc = p["bc"][side]
+        st = bc.get("state", (1.0, 0.0, 0.0, 1.0))
+        c.bc[side] = _Bc(BC_KINDS[bc["kind"]], *[float(v) for v in st])
+    return c
+
+
+def footprint(p: dict) -> int:
+    out = ctypes.c_size_t(0)
+    _check(_lib.mrtfd_footprint(ctypes.byref(c_params(p)), ctypes.byref(out)))
+    return int(out.value)
+
+
+def constants(eta0: float = 2.5):
+    """Dense M and M^-1 as the kernels apply them (host-only)."""
+    M = np.zeros(256)
+    Mi = np.zeros(256)
+    _check(_lib.mrtfd_constants(eta0, M.ctypes.data_as(_dp), Mi.ctypes.data_as(_dp)))
+    return M.reshape(16, 16), Mi.reshape(16, 16)
+
+
+def _is_device(a) -> bool:
+    return hasattr(a, "is_cuda") and bool(a.is_cuda)
+
+
+def _ptr(a, shape, writable=False):
+    """(pointer, on_device, keepalive) for a numpy array or a CUDA tensor."""
+    if a is None:
+        return None, 0, None
+    if _is_device(a):
+        import torch
+        if a.dtype != torch.float64 or not a.is_contiguous() or tuple(a.shape) != tuple(shape):
+            raise ValueError(f"device tensor must be contiguous float64 of shape {shape}")
+        return a.data_ptr(), 1, a
+    arr = np.asarray(a)
+    if writable:
+        if arr.dtype != np.float64 or not arr.flags.c_contiguous or arr.shape != tuple(shape):
+            raise ValueError(f"host output must be contiguous float64 of shape {shape}")
+    else:
+        arr = np.ascontiguousarray(np.broadcast_to(arr.astype(np.float64, copy=False), shape))
+    return arr.ctypes.data, 0, arr
+
+
+def _default_stream():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return torch.cuda.current_stream().cuda_stream
+    except Exception:
+        pass
+    return 0
+
+
+class Solver:
+    """One MRT-FD simulation resident on the GPU."""
+
+    def __init__(self, params: dict, stream=None):
+        self.params = dict(params)
+        self.nx, self.ny = int(params["nx"]), int(params["ny"])
+        if stream is None:
+            stream = _default_stream()
+        elif hasattr(stream, "cuda_stream"):
+            stream = stream.cuda_stream
+        self.stream = int(stream)
+        self._h = _H()
+        self._cp = c_params(params)
+        _check(_lib.mrtfd_create(ctypes.byref(self._cp), _vp(self.stream), ctypes.byref(self._h)))
+
+    # -- lifecycle ------------------------------------------------------------
+    def close(self):
+        if self._h:
+            _lib.mrtfd_destroy(self._h)
+            self._h = _H()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- the path -------------------------------------------------------------
+    def init(self, rho, ux, uy, T):
+        shp = (self.ny, self.nx)
+        ptrs = [_ptr(a, shp) for a in (rho, ux, uy, T)]
+        dev = {p[1] for p in ptrs}
+        if len(dev) != 1:
+            raise ValueError("mix of host and device inputs")
+        _check(_lib.mrtfd_init(self._h, *[_vp(p[0]) for p in ptrs], dev.pop()))
+        return self
+
+    def step(self, nsteps: int = 1):
+        _check(_lib.mrtfd_step(self._h, int(nsteps)))
+        return self
+
+    def step_timed(self, nsteps: int) -> float:
+        ms = ctypes.c_double(0.0)
+        _check(_lib.mrtfd_step_timed(self._h, int(nsteps), ctypes.byref(ms)))
+        return ms.value
+
+    def sync(self):
+        _check(_lib.mrtfd_sync(self._h))
+        return self
+
+    @property
+    def steps_done(self) -> int:
+        return int(_lib.mrtfd_steps_done(self._h))
+
+    # -- outputs --------------------------------------------------------------
+    def macros(self, out=None):
+        """(rho, ux, uy, T) as numpy arrays, or written into ``out`` (4
+        device tensors / host arrays, any may be None)."""
+        shp = (self.ny, self.nx)
+        if out is None:
+            out = tuple(np.zeros(shp) for _ in range(4))
+        ptrs = [_ptr(a, shp, writable=True) for a in out]
+        dev = {p[1] for p in ptrs if p[2] is not None}
+        on_dev = dev.pop() if dev else 0
+        _check(_lib.mrtfd_macros(self._h, *[_vp(p[0]) if p[0] else None for p in ptrs], on_dev))
+        return out
+
+    def noneq(self, star: bool = False, out=None):
+        shp = (16, self.ny, self.nx)
+        if out is None:
+            out = np.zeros(shp)
+        p, dev, _ = _ptr(out, shp, writable=True)
+        _check(_lib.mrtfd_noneq(self._h, 1 if star else 0, _vp(p), dev))
+        return out
+
+    def get_f(self, out=None):
+        shp = (16, self.ny, self.nx)
+        if out is None:
+            out = np.zeros(shp)
+        p, dev, _ = _ptr(out, shp, writable=True)
+        _check(_lib.mrtfd_get_f(self._h, _vp(p), dev))
+        return out
+
+    def set_f(self, f):
+        p, dev, keep = _ptr(f, (16, self.ny, self.nx))
+        _check(_lib.mrtfd_set_f(self._h, _vp(p), dev))
+        return self

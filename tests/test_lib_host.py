@@ -1,0 +1,66 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports
+every entry point include/mrtfd.h declares, its factored constants give the
+paper's M (Appendix) and a true inverse, and parameter validation rejects
+what it should."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1305_4736_amd import build
+    if not os.path.exists(build.LIB):
+        build.build()
+    from paper_1305_4736_amd import mrtfd
+    return mrtfd
+
+
+def declared_symbols():
+    txt = open(os.path.join(ROOT, "include", "mrtfd.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(mrtfd_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_symbols()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(lib._lib, n), n
+
+
+def test_factored_constants_are_the_papers_matrix(lib, orc):
+    M, Mi = lib.constants(2.5)
+    _, Mo, Mio, _ = orc.constants(2.5)
+    assert np.abs(M - Mo).max() <= 1e-13 * np.abs(Mo).max()
+    assert np.abs(M @ Mi - np.eye(16)).max() < 1e-13
+    assert np.abs(Mi @ M - np.eye(16)).max() < 1e-13
+    assert np.abs(Mi - Mio).max() < 1e-14
+
+
+def _ok_params():
+    from paper_1305_4736_amd import workloads as W
+    return W.sod()["params"]
+
+
+def test_footprint_and_validation(lib):
+    p = _ok_params()
+    nbytes = lib.footprint(p)
+    # two buffers of 16 padded planes: (ny + 4) rows of >= nx + 4 doubles
+    assert nbytes >= 2 * 16 * (p["ny"] + 4) * (p["nx"] + 4) * 8
+    bad = []
+    q = dict(p); q["dt"] = p["dx"] / 5.0; bad.append(q)                          # Courant > 1
+    q = dict(p); q["bc"] = [p["bc"][0], {"kind": "periodic"}] + p["bc"][2:]; bad.append(q)
+    q = dict(p); q["s"] = [1e9] * 16; bad.append(q)                              # dt s >= 2
+    q = dict(p); q["nx"] = 0; bad.append(q)
+    q = dict(p); q["bc"] = [{"kind": "wall", "state": (1, 0, 0, 1)}] * 4; bad.append(q)   # walls on both axes
+    q = dict(p); q["limiter"] = "mc"; q["b"] = -1.0; bad.append(q)
+    for q in bad:
+        with pytest.raises(lib.MRTFDError) as e:
+            lib.footprint(q)
+        assert e.value.code == lib.EINVAL
+        assert lib._lib.mrtfd_last_error().decode()
