@@ -1,0 +1,215 @@
+#!/usr/bin/env python3
+"""Benchmark of the fused D2V16 MRT-FD step on one MI355X.
+
+Workload: the heavy/light shock-interface problem on a 4096 x 1024 grid
+(Mach-2 shock in rho = 5 gas, sinusoidal interface to rho = 1 gas, inflow /
+outflow in x, periodic in y, MC limiter), FP64 storage, with the Delta*
+fields computed every 100 steps.  A "step" is one explicit stage of the
+whole grid; value = interior node-updates per second over the timed steps,
+inputs resident in HBM.
+
+Printed: ONE JSON line with the contract fields plus
+  roofline     -- the step kernel's algorithmic HBM bytes per launch
+                  (16 reads + 16 writes of f per node) over its average
+                  launch time, measured with HIP events on the library's
+                  stream inside the timed region; traffic from the committed
+                  rocprofv3 counter summary when it matches the current kernel
+  cpu_baseline -- the FP64 oracle on the host, on a bounded sample of the
+                  same workload (a few full-grid steps)
+  fp32_storage -- the same workload with f stored and convected in FP32.
+
+Options --pmc-copy-calibration and --no-cpu-baseline serve the profiling
+runs (see profiles/).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "node-updates/s (D2V16 MRT-FD) + % HBM peak; p50/p99 served-solve latency"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_step_shock_interface_4096x1024.json")
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1305_4736_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as fh:
+            h.update(name.encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes_per_node(precision: str) -> int:
+    return 32 * (8 if precision == "fp64" else 4)
+
+
+def run_gpu(case, steps, warmup, noneq_every, log):
+    import torch
+
+    from paper_1305_4736_amd import mrtfd
+
+    p = case["params"]
+    nx, ny = p["nx"], p["ny"]
+    dev = torch.device("cuda:0")
+    fields = [torch.tensor(case[k], dtype=torch.float64, device=dev) for k in ("rho", "ux", "uy", "T")]
+    delta = torch.empty((16, ny, nx), dtype=torch.float64, device=dev) if noneq_every else None
+    s = mrtfd.Solver(p, stream=torch.cuda.current_stream())
+    s.init(*fields)
+    del fields
+    s.step(warmup)
+    s.sync()
+    torch.cuda.synchronize()
+    log(f"[bench] {case['name']} {p['precision']}: warm-up {warmup} steps done")
+
+    kernel_ms = 0.0
+    done = 0
+    t0 = time.perf_counter()
+    while done < steps:
+        chunk = min(noneq_every or steps, steps - done)
+        kernel_ms += s.step_timed(chunk)
+        done += chunk
+        if noneq_every and done % noneq_every == 0:
+            s.noneq(star=True, out=delta)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    s.sync()
+    elapsed = t1 - t0
+    nodes = nx * ny
+    res = {
+        "elapsed_s": elapsed,
+        "ms_per_step": 1e3 * elapsed / steps,
+        "value": nodes * steps / elapsed,
+        "kernel_ms_avg": kernel_ms / steps,
+        "nodes": nodes,
+    }
+    s.close()
+    del delta
+    torch.cuda.empty_cache()
+    log(f"[bench] {case['name']} {p['precision']}: {steps} steps in {elapsed:.3f} s, "
+        f"{res['value']:.4e} node-updates/s, kernel {res['kernel_ms_avg']:.4f} ms")
+    return res
+
+
+def roofline(res, precision):
+    bytes_launch = algorithmic_bytes_per_node(precision) * res["nodes"]
+    achieved = bytes_launch / (res["kernel_ms_avg"] * 1e-3) / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+        if t.get("kernel_hash") == kernel_hash() and t.get("precision") == precision:
+            traffic = t["hbm_bytes_per_launch"]
+    return {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "algorithmic_bytes_per_launch": bytes_launch, "kernel": "k_step",
+            "avg_launch_ms": round(res["kernel_ms_avg"], 5)}
+
+
+def cpu_baseline(log, nsteps=2):
+    """The FP64 oracle (serial C) on `nsteps` steps of the full grid."""
+    import oracle
+    from paper_1305_4736_amd import workloads as W
+
+    case = W.shock_interface()
+    p = case["params"]
+    f = oracle.init(p, case["rho"], case["ux"], case["uy"], case["T"])
+    t0 = time.perf_counter()
+    oracle.advance(p, f, nsteps)
+    dt = time.perf_counter() - t0
+    nodes = p["nx"] * p["ny"]
+    log(f"[bench] cpu oracle: {nsteps} full-grid steps in {dt:.1f} s")
+    return {"value": nodes * nsteps / dt, "unit": "node-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{nsteps} steps of the full {p['nx']}x{p['ny']} grid, serial FP64 C oracle "
+                      f"(gcc -O2), {dt:.1f} s"}
+
+
+def copy_calibration(log, nbytes=1 << 30):
+    """A plain device copy of known size, for scaling rocprofv3 byte counters."""
+    import torch
+    n = nbytes // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"[bench] copy calibration: 3 copies of {nbytes} bytes")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--noneq-every", type=int, default=100)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--pmc-copy-calibration", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
+              "the multi-GPU decomposition is described in DESIGN.md but not built.", file=sys.stderr)
+        sys.exit(2)
+
+    log = lambda m: print(m, file=sys.stderr, flush=True)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+
+    from paper_1305_4736_amd import workloads as W
+
+    if args.pmc_copy_calibration:
+        copy_calibration(log)
+
+    case = W.shock_interface(precision="fp64")
+    res = run_gpu(case, args.steps, args.warmup, args.noneq_every, log)
+    rl = roofline(res, "fp64")
+
+    extra = {}
+    if not args.no_fp32:
+        case32 = W.shock_interface(precision="fp32")
+        r32 = run_gpu(case32, args.steps, args.warmup, args.noneq_every, log)
+        rl32 = roofline(r32, "fp32")
+        extra["fp32_storage"] = {"value": r32["value"], "ms_per_step": r32["ms_per_step"],
+                                 "roofline_frac": rl32["frac"], "achieved_GBs": rl32["achieved"],
+                                 "speedup_vs_fp64": r32["value"] / res["value"]}
+
+    cpu = None if args.no_cpu_baseline else cpu_baseline(log)
+
+    line = {
+        "metric": METRIC,
+        "value": res["value"],
+        "unit": "node-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": res["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "shock_interface_4096x1024", "grid": [4096, 1024], "precision": "fp64",
+                   "limiter": "mc", "noneq_star_every": args.noneq_every, "gamma": 1.4,
+                   "boundaries": "inflow / outflow in x, periodic in y"},
+        "roofline": rl,
+        "cpu_baseline": cpu,
+        **extra,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -38,6 +38,34 @@ enum { BC_PERIODIC = MRTFD_BC_PERIODIC, BC_EQUIL = MRTFD_BC_EQUILIBRIUM, BC_OUTF
 
 constexpr int BX = 64;   // threads along x per block (one wavefront)
 constexpr int BY = 4;    // rows per block
+// Step-kernel tile (nodes per block = threads per block): TXW x BYR.
+#ifndef STEP_TXW64
+#define STEP_TXW64 32
+#endif
+#ifndef STEP_BYR64
+#define STEP_BYR64 4
+#endif
+#ifndef STEP_TXW32
+#define STEP_TXW32 32
+#endif
+#ifndef STEP_BYR32
+#define STEP_BYR32 8
+#endif
+template <typename T> struct TileOf;
+template <> struct TileOf<double> { static constexpr int TXW = STEP_TXW64, BYR = STEP_BYR64; };
+template <> struct TileOf<float> { static constexpr int TXW = STEP_TXW32, BYR = STEP_BYR32; };
+#ifndef STEP_WAVES_PER_SIMD
+#define STEP_WAVES_PER_SIMD 4
+#endif
+#ifndef STEP_PREFETCH
+#define STEP_PREFETCH 4   // planes staged ahead in registers
+#endif
+#ifndef STEP_BAND
+#define STEP_BAND (1 << 20)   // tile columns per band of the XCD-aware tile order (default: whole rows)
+#endif
+#ifndef STEP_PLANE_FENCE
+#define STEP_PLANE_FENCE() __builtin_amdgcn_sched_barrier(0)
+#endif
 
 __device__ __forceinline__ long node(const StepArgs& a, int x, int y)
 {
@@ -64,12 +92,12 @@ template <typename T>
 __device__ void wall_fill(const StepArgs& a, T* __restrict__ f, const double* f1, int side, long nw, long step)
 {
     double r1, u1x, u1y, T1;
-    macro_of(a.B, a.inv_b, f1, r1, u1x, u1y, T1);
+    macro_of(*a.Bp, a.inv_b, f1, r1, u1x, u1y, T1);
     const double* st = a.side[side];
     double rw = r1 * T1 / st[3];           // carry the pressure over: rho_w T_w = rho_1 T_1
     double ew[NQ], e1[NQ];
-    feq_velocity(a.B, a.b, rw, st[1], st[2], st[3], ew);
-    feq_velocity(a.B, a.b, r1, u1x, u1y, T1, e1);
+    feq_velocity(*a.Bp, a.b, rw, st[1], st[2], st[3], ew);
+    feq_velocity(*a.Bp, a.b, r1, u1x, u1y, T1, e1);
 #pragma unroll
     for (int i = 0; i < NQ; ++i) {
         double fw = ew[i] + (f1[i] - e1[i]);
@@ -80,35 +108,14 @@ __device__ void wall_fill(const StepArgs& a, T* __restrict__ f, const double* f1
 }
 
 // ---------------------------------------------------------------------------
-// The fused step.
-template <int LIM, typename T>
-__global__ void __launch_bounds__(BX * BY) k_step(const T* __restrict__ fin, T* __restrict__ fout, StepArgs a)
+// The fused step, per node.
+
+// Relaxed residual of the non-conserved moments, mapped back to velocity
+// space and scaled by -dt (the collision term of the update).
+__device__ __forceinline__ void collision(const StepArgs& a, const double* m, double rho, double ux, double uy,
+                                          double P, bool corr, double dxux, double dxuy, double dyux,
+                                          double dyuy, double* coll)
 {
-    using R = T;   // convection precision (FP64, or FP32 in FP32-storage mode)
-    const int x = a.x0 + blockIdx.x * BX + threadIdx.x;
-    const int y = a.y0 + blockIdx.y * BY + threadIdx.y;
-    if (x >= a.x1 || y >= a.y1) return;
-    const long n0 = node(a, x, y);
-
-    T fT[NQ];
-    double f[NQ];
-#pragma unroll
-    for (int i = 0; i < NQ; ++i) {
-        fT[i] = fin[i * a.plane + n0];
-        f[i] = (double)fT[i];
-    }
-
-    // moments and macroscopic state
-    double m[NQ];
-    Sums sm = all_sums(f);
-    moments(a.B, sm, m);
-    const double rho = m[0];
-    const double ir = 1.0 / rho;
-    const double ux = m[1] * ir, uy = m[2] * ir;
-    const double P = (m[3] - rho * (ux * ux + uy * uy)) * a.inv_b;
-    if (!(rho > 0.0 && P > 0.0)) atomicOr(a.flag, 1);
-
-    // relaxed residual of the non-conserved moments
     double eq[NQ];
     equilibria(rho, ux, uy, P, m[3], a.b, eq);
     double w[NQ];
@@ -116,20 +123,8 @@ __global__ void __launch_bounds__(BX * BY) k_step(const T* __restrict__ fin, T* 
     for (int k = 0; k < 4; ++k) w[k] = 0.0;
 #pragma unroll
     for (int k = 4; k < NQ; ++k) w[k] = a.s[k] * (m[k] - eq[k]);
-
-    if (a.correction) {
-        // energy-flux correction: central differences of u at level n
-        double g[NQ], uxw, uyw, uxe, uye, uxs, uys, uxn, uyn;
-        load16(fin, a, n0 - 1, g);
-        velocity_of(a.B, g, uxw, uyw);
-        load16(fin, a, n0 + 1, g);
-        velocity_of(a.B, g, uxe, uye);
-        load16(fin, a, n0 - a.pitch, g);
-        velocity_of(a.B, g, uxs, uys);
-        load16(fin, a, n0 + a.pitch, g);
-        velocity_of(a.B, g, uxn, uyn);
-        const double dxux = (uxe - uxw) * a.inv2dx, dxuy = (uye - uyw) * a.inv2dx;
-        const double dyux = (uxn - uxs) * a.inv2dy, dyuy = (uyn - uys) * a.inv2dy;
+    if (corr) {
+        // energy-flux correction of moments 8 and 9 (central differences of u)
         const double div4b = 4.0 * a.inv_b * (dxux + dyuy);
         const double shear2 = 2.0 * (dxuy + dyux);
         w[7] += a.k8 * P * (ux * (4.0 * dxux - div4b) + uy * shear2);
@@ -137,75 +132,231 @@ __global__ void __launch_bounds__(BX * BY) k_step(const T* __restrict__ fin, T* 
     }
 #pragma unroll
     for (int k = 4; k < NQ; ++k) w[k] *= -a.dt;
-    double coll[NQ];
-    inverse_nc(a.B, w, coll);
+    inverse_nc(*a.Bp, w, coll);
+}
 
-    // limited fluxes, x then y, and the update
-    T fnew[NQ];
+// Limited x and y flux differences of the 16 populations and the update,
+// stored plane by plane (the centre value is re-read with its stencil, so
+// only the 16 collision terms stay live across the loop).
+template <int LIM, typename T>
+__device__ __forceinline__ void convect_update(const T* __restrict__ fin, T* __restrict__ fout, const StepArgs& a,
+                                               long n0, const double* coll)
+{
+    using R = T;   // convection precision (FP64, or FP32 in FP32-storage mode)
 #pragma unroll
     for (int i = 0; i < NQ; ++i) {
         const long pi = i * a.plane + n0;
         const int g = i >> 2;
+        const R f0 = fin[pi];
         R acc = R(0);
         if (sgx(i) != 0) {
             const long s = sgx(i);
-            acc += conv1<LIM, R>(fin[pi - 2 * s], fin[pi - s], fT[i], fin[pi + s], (R)a.nux[g], (R)a.cx[g]);
+            acc += conv1<LIM, R>(fin[pi - 2 * s], fin[pi - s], f0, fin[pi + s], (R)a.nux[g], (R)a.cx[g]);
         }
         if (sgy(i) != 0) {
             const long s = sgy(i) * a.pitch;
-            acc += conv1<LIM, R>(fin[pi - 2 * s], fin[pi - s], fT[i], fin[pi + s], (R)a.nuy[g], (R)a.cy[g]);
+            acc += conv1<LIM, R>(fin[pi - 2 * s], fin[pi - s], f0, fin[pi + s], (R)a.nuy[g], (R)a.cy[g]);
         }
-        fnew[i] = (T)(f[i] + (double)acc + coll[i]);
+        fout[pi] = (T)((double)f0 + (double)acc + coll[i]);
+        STEP_PLANE_FENCE();
     }
-    store16(fout, a, n0, fnew);
+}
 
-    // boundary images owned by this node
+// Periodic and outflow ghost images owned by node (x, y): up to 4 along x
+// and 4 along y (a single-node axis wraps onto all four ghosts).  Returns the
+// count; offs[] are element offsets relative to the node.  Wall nodes and
+// their ghosts are filled afterwards by k_fill (walls only).
+__device__ __forceinline__ int image_offsets(const StepArgs& a, int x, int y, int* offs)
+{
+    int n = 0;
     if (a.bc[0] == BC_PERIODIC) {
         if (x < 2 || x >= a.nx - 2) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int xg = (q < 2) ? (q - 2) : (a.nx + q - 2);
-                if ((((xg % a.nx) + a.nx) % a.nx) == x) store16(fout, a, n0 + (xg - x), fnew);
+                if ((((xg % a.nx) + a.nx) % a.nx) == x) offs[n++] = xg - x;
             }
         }
     } else {
         if (a.bc[0] == BC_OUTFLOW && x == 0) {
-            store16(fout, a, n0 - 1, fnew);
-            store16(fout, a, n0 - 2, fnew);
+            offs[n++] = -1;
+            offs[n++] = -2;
         }
         if (a.bc[1] == BC_OUTFLOW && x == a.nx - 1) {
-            store16(fout, a, n0 + 1, fnew);
-            store16(fout, a, n0 + 2, fnew);
+            offs[n++] = 1;
+            offs[n++] = 2;
         }
     }
+    const int pitch = (int)a.pitch;
     if (a.bc[2] == BC_PERIODIC) {
         if (y < 2 || y >= a.ny - 2) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int yg = (q < 2) ? (q - 2) : (a.ny + q - 2);
-                if ((((yg % a.ny) + a.ny) % a.ny) == y) store16(fout, a, n0 + (long)(yg - y) * a.pitch, fnew);
+                if ((((yg % a.ny) + a.ny) % a.ny) == y) offs[n++] = (yg - y) * pitch;
             }
         }
     } else {
         if (a.bc[2] == BC_OUTFLOW && y == 0) {
-            store16(fout, a, n0 - a.pitch, fnew);
-            store16(fout, a, n0 - 2 * a.pitch, fnew);
+            offs[n++] = -pitch;
+            offs[n++] = -2 * pitch;
         }
         if (a.bc[3] == BC_OUTFLOW && y == a.ny - 1) {
-            store16(fout, a, n0 + a.pitch, fnew);
-            store16(fout, a, n0 + 2 * a.pitch, fnew);
+            offs[n++] = pitch;
+            offs[n++] = 2 * pitch;
         }
     }
-    const bool wy_lo = (a.bc[2] == BC_WALL && y == 1), wy_hi = (a.bc[3] == BC_WALL && y == a.ny - 2);
-    const bool wx_lo = (a.bc[0] == BC_WALL && x == 1), wx_hi = (a.bc[1] == BC_WALL && x == a.nx - 2);
-    if (wy_lo || wy_hi || wx_lo || wx_hi) {
-        double fn[NQ];
+    return n;
+}
+
+// The fused step kernel.  A block owns a TXW x BYR tile of nodes, one node
+// per thread.  It first copies the tile with a two-node halo, all 16 planes,
+// into LDS with every load in flight at once (f is read from HBM once per
+// step; the halo rows come from L2).  After one barrier everything is read
+// from LDS: each node's moments and velocity, the velocity of the one-node
+// ring around the tile, then (second barrier) the central differences of u,
+// the equilibria and the collision term, and the limited x / y flux
+// differences of each plane; the new value of each plane is stored as soon
+// as it is known.  Two blocks per CU alternate between loading and
+// computing.
+//
+// Blocks are assigned round-robin to the 8 XCDs (each with its own L2):
+// block b takes tile t = (b mod 8) * per_xcd + b / 8 of an order that
+// sweeps bands of `band` tile columns row by row, so that the tiles resident
+// on one XCD are neighbours and share their halo rows in its L2.
+template <int LIM, typename T, int TXW, int BYR>
+__global__ void __launch_bounds__(TXW * BYR, 1) k_step(const T* __restrict__ fin, T* __restrict__ fout,
+                                                      StepArgs a)
+{
+    constexpr int TW = TXW + 4, TH = BYR + 4, TN = TW * TH;   // staged tile (with halo)
+    constexpr int NT = TXW * BYR;                              // threads = nodes
+    constexpr int PER = (TN + NT - 1) / NT;                    // staged elements per thread per plane
+    constexpr int UW = TXW + 2;                                // velocity tile width (one-node ring)
+    __shared__ T tile[NQ * TN];
+    __shared__ double sux[(BYR + 2) * UW], suy[(BYR + 2) * UW];
+
+    const int tid = threadIdx.x;
+    const int bid = blockIdx.x;
+    const int t = (bid & 7) * a.per_xcd + (bid >> 3);
+    if (t >= a.ntx * a.nty) return;
+    const int band_tiles = a.band * a.nty;
+    const int bnd = t / band_tiles, rr = t - bnd * band_tiles;
+    const int bw = min(a.band, a.ntx - bnd * a.band);
+    const int tyy = rr / bw, txx = bnd * a.band + (rr - tyy * bw);
+    const int xb = a.x0 + txx * TXW, yb = a.y0 + tyy * BYR;
+    const int ty = tid / TXW, tx = tid - ty * TXW;
+    const int x = xb + tx, y = yb + ty;
+    const bool active = (x < a.x1) && (y < a.y1);
+    const int pitch = (int)a.pitch;
+    const int n0 = (int)a.org + y * pitch + x;     // offset inside a plane
+    const bool corr = a.correction != 0;
+
+    // ---- copy the tile (all planes, two-node halo) into LDS
+    {
+        int soff[PER];
+        bool sok[PER];
 #pragma unroll
-        for (int i = 0; i < NQ; ++i) fn[i] = (double)fnew[i];
-        if (wy_lo) wall_fill(a, fout, fn, 2, n0 - a.pitch, -a.pitch);
-        if (wy_hi) wall_fill(a, fout, fn, 3, n0 + a.pitch, a.pitch);
-        if (wx_lo) wall_fill(a, fout, fn, 0, n0 - 1, -1);
-        if (wx_hi) wall_fill(a, fout, fn, 1, n0 + 1, 1);
+        for (int k = 0; k < PER; ++k) {
+            const int e = tid + k * NT;
+            const int r = e / TW, c = e - r * TW;
+            const int gx = xb - 2 + c, gy = yb - 2 + r;
+            sok[k] = (e < TN) && gx >= -2 && gx <= a.nx + 1 && gy >= -2 && gy <= a.ny + 1;
+            soff[k] = (int)a.org + gy * pitch + gx;
+        }
+        T v[NQ][PER];
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) {
+            const T* pl = fin + (long)i * a.plane;
+#pragma unroll
+            for (int k = 0; k < PER; ++k) v[i][k] = sok[k] ? pl[soff[k]] : T(0);
+        }
+#pragma unroll
+        for (int i = 0; i < NQ; ++i)
+#pragma unroll
+            for (int k = 0; k < PER; ++k)
+                if (tid + k * NT < TN) tile[i * TN + tid + k * NT] = v[i][k];
+    }
+    __syncthreads();
+
+    // ---- moments of the own node, velocity of the own node and of the ring
+    const int c0 = (ty + 2) * TW + tx + 2;           // own position in a staged plane
+    double m[NQ], rho = 1.0, ux = 0.0, uy = 0.0, P = 1.0;
+    {
+        double f[NQ];
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) f[i] = (double)tile[i * TN + c0];
+        Sums sm = all_sums(f);
+        moments(*a.Bp, sm, m);
+        rho = m[0];
+        const double ir = 1.0 / rho;
+        ux = m[1] * ir;
+        uy = m[2] * ir;
+        P = (m[3] - rho * (ux * ux + uy * uy)) * a.inv_b;
+    }
+    double dxux = 0.0, dxuy = 0.0, dyux = 0.0, dyuy = 0.0;
+    if (corr) {
+        sux[(ty + 1) * UW + tx + 1] = ux;
+        suy[(ty + 1) * UW + tx + 1] = uy;
+        if (tid < 2 * TXW + 2 * BYR) {
+            int lx, ly;                                  // ring node in tile coordinates (-1 .. TXW, -1 .. BYR)
+            if (tid < TXW) {
+                lx = tid; ly = -1;
+            } else if (tid < 2 * TXW) {
+                lx = tid - TXW; ly = BYR;
+            } else if (tid < 2 * TXW + BYR) {
+                lx = -1; ly = tid - 2 * TXW;
+            } else {
+                lx = TXW; ly = tid - 2 * TXW - BYR;
+            }
+            double g[NQ], vx = 0.0, vy = 0.0;
+            const int cr = (ly + 2) * TW + lx + 2;
+#pragma unroll
+            for (int i = 0; i < NQ; ++i) g[i] = (double)tile[i * TN + cr];
+            const int rx = xb + lx, ry = yb + ly;
+            if (rx >= a.x0 - 1 && rx <= a.x1 && ry >= a.y0 - 1 && ry <= a.y1) velocity_of(*a.Bp, g, vx, vy);
+            sux[(ly + 1) * UW + lx + 1] = vx;
+            suy[(ly + 1) * UW + lx + 1] = vy;
+        }
+        __syncthreads();
+        const int cu = (ty + 1) * UW + tx + 1;
+        dxux = (sux[cu + 1] - sux[cu - 1]) * a.inv2dx;
+        dxuy = (suy[cu + 1] - suy[cu - 1]) * a.inv2dx;
+        dyux = (sux[cu + UW] - sux[cu - UW]) * a.inv2dy;
+        dyuy = (suy[cu + UW] - suy[cu - UW]) * a.inv2dy;
+    }
+    if (!active) return;
+    if (!(rho > 0.0 && P > 0.0)) atomicOr(a.flag, 1);
+    double coll[NQ];
+    collision(a, m, rho, ux, uy, P, corr, dxux, dxuy, dyux, dyuy, coll);
+
+    // ---- limited fluxes and the update, plane by plane
+    using R = T;   // convection precision (FP64, or FP32 in FP32-storage mode)
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+        const T* tb = tile + i * TN;
+        const int g = i >> 2;
+        const R f0 = tb[c0];
+        R acc = R(0);
+        if (sgx(i) != 0) {
+            const int sx = sgx(i);
+            acc += conv1<LIM, R>(tb[c0 - 2 * sx], tb[c0 - sx], f0, tb[c0 + sx], (R)a.nux[g], (R)a.cx[g]);
+        }
+        if (sgy(i) != 0) {
+            const int sy = sgy(i) * TW;
+            acc += conv1<LIM, R>(tb[c0 - 2 * sy], tb[c0 - sy], f0, tb[c0 + sy], (R)a.nuy[g], (R)a.cy[g]);
+        }
+        fout[(long)i * a.plane + n0] = (T)((double)f0 + (double)acc + coll[i]);
+    }
+
+    int offs[8];
+    const int nimg = image_offsets(a, x, y, offs);
+    if (nimg > 0) {
+        // copy this thread's own new values (same thread, same addresses)
+        for (int i = 0; i < NQ; ++i) {
+            T* pl = fout + (long)i * a.plane;
+            const T v = pl[n0];
+            for (int q = 0; q < nimg; ++q) pl[n0 + offs[q]] = v;
+        }
     }
 }
 
@@ -219,7 +370,7 @@ __global__ void k_init(T* __restrict__ f, const double* __restrict__ rho, const 
     if (x >= a.nx || y >= a.ny) return;
     const long d = (long)y * a.nx + x;
     double fe[NQ];
-    feq_velocity(a.B, a.b, rho[d], ux[d], uy[d], Tf[d], fe);
+    feq_velocity(*a.Bp, a.b, rho[d], ux[d], uy[d], Tf[d], fe);
     const long n = node(a, x, y);
 #pragma unroll
     for (int i = 0; i < NQ; ++i) f[i * a.plane + n] = (T)fe[i];
@@ -228,7 +379,7 @@ __global__ void k_init(T* __restrict__ f, const double* __restrict__ rho, const 
 // Ghost fill of one axis from the interior (x-sides over rows, then y-sides
 // over columns, two launches); used after init and set_f.
 template <typename T>
-__global__ void k_fill(T* __restrict__ f, StepArgs a, int axis)
+__global__ void k_fill(T* __restrict__ f, StepArgs a, int axis, int walls_only)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const int n_line = (axis == 0) ? a.ny : a.nx;
@@ -240,6 +391,7 @@ __global__ void k_fill(T* __restrict__ f, StepArgs a, int axis)
     const long stride = (axis == 0) ? 1 : a.pitch;
     const long base = (axis == 0) ? node(a, 0, line) : node(a, line, 0);   // node at coordinate 0
     const int kind = a.bc[side];
+    if (walls_only && kind != BC_WALL) return;
     double v[NQ];
     if (kind == BC_WALL) {
         const int c1 = side_lo ? 1 : n - 2, cw = side_lo ? 0 : n - 1;
@@ -249,7 +401,7 @@ __global__ void k_fill(T* __restrict__ f, StepArgs a, int axis)
     }
     if (kind == BC_EQUIL) {
         const double* st = a.side[side];
-        feq_velocity(a.B, a.b, st[0], st[1], st[2], st[3], v);
+        feq_velocity(*a.Bp, a.b, st[0], st[1], st[2], st[3], v);
     }
     for (int k = 1; k <= 2; ++k) {
         const int cg = side_lo ? -k : n - 1 + k;
@@ -267,7 +419,7 @@ __global__ void k_macros(const T* __restrict__ f, double* rho, double* ux, doubl
     if (x >= a.nx || y >= a.ny) return;
     double v[NQ], r, vx, vy, t;
     load16(f, a, node(a, x, y), v);
-    macro_of(a.B, a.inv_b, v, r, vx, vy, t);
+    macro_of(*a.Bp, a.inv_b, v, r, vx, vy, t);
     const long d = (long)y * a.nx + x;
     if (rho) rho[d] = r;
     if (ux) ux[d] = vx;
@@ -285,7 +437,7 @@ __global__ void k_noneq(const T* __restrict__ f, int star, double* __restrict__ 
     double v[NQ], m[NQ], eq[NQ], dl[NQ];
     load16(f, a, node(a, x, y), v);
     Sums sm = all_sums(v);
-    moments(a.B, sm, m);
+    moments(*a.Bp, sm, m);
     const double rho = m[0], ir = 1.0 / rho, ux = m[1] * ir, uy = m[2] * ir;
     const double P = (m[3] - rho * (ux * ux + uy * uy)) * a.inv_b;
     equilibria(rho, ux, uy, P, m[3], a.b, eq);
@@ -300,13 +452,13 @@ __global__ void k_noneq(const T* __restrict__ f, int star, double* __restrict__ 
         return;
     }
     double gq[NQ], ds[NQ];
-    inverse_nc(a.B, dl, gq);
+    inverse_nc(*a.Bp, dl, gq);
 #pragma unroll
     for (int k = 0; k < NQ; ++k) ds[k] = 0.0;
 #pragma unroll
     for (int i = 0; i < NQ; ++i) {
         const int g = i >> 2;
-        const double cx = sgx(i) * a.B.vmag[g] - ux, cy = sgy(i) * a.B.vmag[g] - uy;
+        const double cx = sgx(i) * a.Bp->vmag[g] - ux, cy = sgy(i) * a.Bp->vmag[g] - uy;
         const double c2 = cx * cx + cy * cy, ce = c2 + ((g == 0) ? eta0 * eta0 : 0.0);
         const double dxy = cx * cx - cy * cy, q = gq[i];
         ds[0] += q;
@@ -430,6 +582,9 @@ int validate(const mrtfd_params* p)
     if (p->dt * smax >= 2.0) return fail(MRTFD_EINVAL, "dt * max(s) = %.4g must be < 2", p->dt * smax);
     if (p->energy_flux_correction && !(p->s[4] > 0)) return fail(MRTFD_EINVAL, "the correction needs s_5 > 0");
     if (!(p->eta0 >= 0)) return fail(MRTFD_EINVAL, "eta0 must be >= 0");
+    const Layout L = layout_of(*p);
+    if (L.plane >= (1L << 31))
+        return fail(MRTFD_EINVAL, "grid %d x %d too large: a padded plane must stay below 2^31 elements", p->nx, p->ny);
     return MRTFD_OK;
 }
 
@@ -445,6 +600,8 @@ struct mrtfd_s {
     double* staging;
     size_t staging_bytes;
     StepArgs args;
+    Blocks blocks;          // host copy
+    Blocks* blocks_dev;     // device copy read by the kernels
     bool ready;
     long steps;
     hipEvent_t ev0, ev1;
@@ -457,14 +614,14 @@ void fill_args(mrtfd_s* h)
     const mrtfd_params& p = h->p;
     StepArgs& a = h->args;
     std::memset(&a, 0, sizeof(a));
-    build_blocks(p.eta0, &a.B);
+    a.Bp = h->blocks_dev;
     for (int k = 0; k < NQ; ++k) a.s[k] = p.s[k];
     a.b = p.b;
     a.inv_b = 1.0 / p.b;
     a.dt = p.dt;
     for (int g = 0; g < 4; ++g) {
-        a.nux[g] = a.B.vmag[g] * p.dt / p.dx;
-        a.nuy[g] = a.B.vmag[g] * p.dt / p.dy;
+        a.nux[g] = h->blocks.vmag[g] * p.dt / p.dx;
+        a.nuy[g] = h->blocks.vmag[g] * p.dt / p.dy;
         a.cx[g] = 0.5 * (1.0 - a.nux[g]);
         a.cy[g] = 0.5 * (1.0 - a.nuy[g]);
     }
@@ -489,6 +646,12 @@ void fill_args(mrtfd_s* h)
     a.x1 = p.nx - (p.bc[1].kind == BC_WALL);
     a.y0 = (p.bc[2].kind == BC_WALL);
     a.y1 = p.ny - (p.bc[3].kind == BC_WALL);
+    const int txw = (p.precision == MRTFD_FP32_STORAGE) ? STEP_TXW32 : STEP_TXW64;
+    const int byr = (p.precision == MRTFD_FP32_STORAGE) ? STEP_BYR32 : STEP_BYR64;
+    a.ntx = (a.x1 - a.x0 + txw - 1) / txw;
+    a.nty = (a.y1 - a.y0 + byr - 1) / byr;
+    a.per_xcd = (a.ntx * a.nty + 7) / 8;
+    a.band = STEP_BAND;
     a.flag = h->flag;
 }
 
@@ -519,14 +682,21 @@ int launch_step_t(mrtfd_s* h)
     T* fout = (T*)h->buf[1 - h->cur];
     const int ex = a.x1 - a.x0, ey = a.y1 - a.y0;
     if (ex > 0 && ey > 0) {
-        dim3 grid = node_grid(ex, ey), block(BX, BY);
+        constexpr int TXW = TileOf<T>::TXW, BYR = TileOf<T>::BYR;
+        dim3 grid(8 * a.per_xcd), block(TXW * BYR);
         switch (h->p.limiter) {
-        case 0: hipLaunchKernelGGL((k_step<0, T>), grid, block, 0, h->stream, fin, fout, a); break;
-        case 1: hipLaunchKernelGGL((k_step<1, T>), grid, block, 0, h->stream, fin, fout, a); break;
-        case 2: hipLaunchKernelGGL((k_step<2, T>), grid, block, 0, h->stream, fin, fout, a); break;
-        default: hipLaunchKernelGGL((k_step<3, T>), grid, block, 0, h->stream, fin, fout, a); break;
+        case 0: hipLaunchKernelGGL((k_step<0, T, TXW, BYR>), grid, block, 0, h->stream, fin, fout, a); break;
+        case 1: hipLaunchKernelGGL((k_step<1, T, TXW, BYR>), grid, block, 0, h->stream, fin, fout, a); break;
+        case 2: hipLaunchKernelGGL((k_step<2, T, TXW, BYR>), grid, block, 0, h->stream, fin, fout, a); break;
+        default: hipLaunchKernelGGL((k_step<3, T, TXW, BYR>), grid, block, 0, h->stream, fin, fout, a); break;
         }
         HIPCHK(hipGetLastError());
+        for (int axis = 0; axis < 2; ++axis) {
+            if (a.bc[2 * axis] != BC_WALL && a.bc[2 * axis + 1] != BC_WALL) continue;
+            const int n = 2 * ((axis == 0) ? a.ny : a.nx);
+            hipLaunchKernelGGL((k_fill<T>), dim3((n + 127) / 128), dim3(128), 0, h->stream, fout, a, axis, 1);
+            HIPCHK(hipGetLastError());
+        }
     }
     h->cur = 1 - h->cur;
     return MRTFD_OK;
@@ -543,7 +713,7 @@ int refill_t(mrtfd_s* h)
     T* f = (T*)h->buf[h->cur];
     for (int axis = 0; axis < 2; ++axis) {
         const int n = 2 * ((axis == 0) ? h->p.ny : h->p.nx);
-        hipLaunchKernelGGL((k_fill<T>), dim3((n + 127) / 128), dim3(128), 0, h->stream, f, h->args, axis);
+        hipLaunchKernelGGL((k_fill<T>), dim3((n + 127) / 128), dim3(128), 0, h->stream, f, h->args, axis, 0);
         HIPCHK(hipGetLastError());
     }
     // both buffers carry the (constant) equilibrium ghosts
@@ -592,14 +762,24 @@ int mrtfd_create(const mrtfd_params* p, void* hip_stream, mrtfd_t* out)
             return fail(MRTFD_ENOMEM, "cannot allocate 2 x %zu bytes of state", h->L.buf_bytes);
         }
     }
-    if (hipMalloc(&h->flag, sizeof(int)) != hipSuccess || hipEventCreate(&h->ev0) != hipSuccess ||
-        hipEventCreate(&h->ev1) != hipSuccess) {
+    if (!build_blocks(p->eta0, &h->blocks)) {
+        (void)hipFree(h->buf[0]);
+        (void)hipFree(h->buf[1]);
+        delete h;
+        return fail(MRTFD_EINVAL, "singular moment blocks for eta0 = %g", p->eta0);
+    }
+    if (hipMalloc(&h->flag, sizeof(int)) != hipSuccess || hipMalloc(&h->blocks_dev, sizeof(Blocks)) != hipSuccess ||
+        hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess) {
         (void)hipFree(h->buf[0]);
         (void)hipFree(h->buf[1]);
         delete h;
         return fail(MRTFD_EDEVICE, "device set-up failed");
     }
     fill_args(h);
+    if (hipMemcpyAsync(h->blocks_dev, &h->blocks, sizeof(Blocks), hipMemcpyHostToDevice, h->stream) != hipSuccess) {
+        mrtfd_destroy(h);
+        return fail(MRTFD_EDEVICE, "device set-up failed");
+    }
     if (hipMemsetAsync(h->flag, 0, sizeof(int), h->stream) != hipSuccess ||
         hipMemsetAsync(h->buf[0], 0, h->L.buf_bytes, h->stream) != hipSuccess ||
         hipMemsetAsync(h->buf[1], 0, h->L.buf_bytes, h->stream) != hipSuccess) {
@@ -617,6 +797,7 @@ int mrtfd_destroy(mrtfd_t h)
     (void)hipFree(h->buf[0]);
     (void)hipFree(h->buf[1]);
     (void)hipFree(h->flag);
+    (void)hipFree(h->blocks_dev);
     if (h->staging) (void)hipFree(h->staging);
     (void)hipEventDestroy(h->ev0);
     (void)hipEventDestroy(h->ev1);

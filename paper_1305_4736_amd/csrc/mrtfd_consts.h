@@ -85,17 +85,20 @@ static bool build_blocks(double eta0, Blocks* out)
     if (!invert_small<4>(F0, I0) || !invert_small<4>(FX, IX) || !invert_small<4>(FY, IY) ||
         !invert_small<2>(FDa, IDa) || !invert_small<2>(FDd, IDd))
         return false;
+    // the Y block is the X block with its last row negated, so its inverse is
+    // the X inverse with its last column negated
+    for (int r = 0; r < 4; ++r)
+        for (int k = 0; k < 4; ++k)
+            if (fabsl(IY[r][k] - (k == 3 ? -IX[r][k] : IX[r][k])) > 1e-15L * (1.0L + fabsl(IX[r][k]))) return false;
     Blocks& B = *out;
     std::memset(&B, 0, sizeof(B));
     for (int r = 0; r < 4; ++r)
         for (int c = 0; c < 4; ++c) {
             B.F0[r][c] = (double)F0[r][c];
             B.FX[r][c] = (double)FX[r][c];
-            B.FY[r][c] = (double)FY[r][c];
             long double sx = (r < 2) ? 0.5L : 0.25L;   // row r of an inverse is group r
             B.I0[r][c] = (double)(0.25L * I0[r][c]);
             B.IX[r][c] = (double)(sx * IX[r][c]);
-            B.IY[r][c] = (double)(sx * IY[r][c]);
         }
     for (int r = 0; r < 2; ++r)
         for (int c = 0; c < 2; ++c) {

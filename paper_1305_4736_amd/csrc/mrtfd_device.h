@@ -31,20 +31,21 @@ __host__ __device__ constexpr int sgy(int i)
 
 // Forward blocks: rows of M acting on the per-group sums.
 //   F0: (m_1, m_4, m_5, m_14) from S_g        FX: (m_2, m_8, m_10, m_12) from X_g
-//   FY: (m_3, m_9, m_11, m_13) from Y_g       FDa: (m_6, m_16) from D_0, D_1
-//   FDd: (m_7, m_15) from D_2, D_3
+//   (m_3, m_9, m_11, m_13) from Y_g are FX with the last row negated
+//   FDa: (m_6, m_16) from D_0, D_1            FDd: (m_7, m_15) from D_2, D_3
 // Inverse blocks (already carrying the inverse angular-sum factors 1/4, 1/2):
 //   I0[g][c]  : S'_g from column c of (m_1, m_4, m_5, m_14)
-//   IX[g][c], IY[g][c], IDa[g][c], IDd[g][c] likewise.
+//   IX[g][c], IDa[g][c], IDd[g][c] likewise; the Y block is IX with its last
+//   column negated.
 struct Blocks {
-    double F0[4][4], FX[4][4], FY[4][4], FDa[2][2], FDd[2][2];
-    double I0[4][4], IX[4][4], IY[4][4], IDa[2][2], IDd[2][2];
+    double F0[4][4], FX[4][4], FDa[2][2], FDd[2][2];
+    double I0[4][4], IX[4][4], IDa[2][2], IDd[2][2];
     double vmag[4];     // |v_x| (= |v_y|) of a moving component, per group
 };
 
 // Everything a step needs that is uniform over the grid.
 struct StepArgs {
-    Blocks B;
+    const Blocks* __restrict__ Bp;   // device copy of the blocks (read with scalar loads)
     double s[NQ];
     double b, inv_b, dt;
     double nux[4], nuy[4];      // Courant numbers |v_ia| dt / d_a per group
@@ -57,6 +58,9 @@ struct StepArgs {
     long plane;                 // elements per padded plane
     long org;                   // element offset of node (0, 0) inside a plane
     int x0, x1, y0, y1;         // evolved node range [x0, x1) x [y0, y1)
+    int ntx, nty;               // step-kernel tiles along x and y
+    int per_xcd;                // tiles per XCD slot (grid = 8 * per_xcd blocks)
+    int band;                   // tile columns per band of the XCD-aware order
     int bc[4];                  // kinds of x-lo, x-hi, y-lo, y-hi
     int correction;
     int* flag;                  // set to 1 when a node is unphysical
@@ -131,10 +135,10 @@ __host__ __device__ __forceinline__ void moments(const Blocks& B, const Sums& a,
     m[7] = dot4(B.FX[1], a.X);
     m[9] = dot4(B.FX[2], a.X);
     m[11] = dot4(B.FX[3], a.X);
-    m[2] = dot4(B.FY[0], a.Y);
-    m[8] = dot4(B.FY[1], a.Y);
-    m[10] = dot4(B.FY[2], a.Y);
-    m[12] = dot4(B.FY[3], a.Y);
+    m[2] = dot4(B.FX[0], a.Y);
+    m[8] = dot4(B.FX[1], a.Y);
+    m[10] = dot4(B.FX[2], a.Y);
+    m[12] = -dot4(B.FX[3], a.Y);
     m[5] = fma(B.FDa[0][0], a.D[0], B.FDa[0][1] * a.D[1]);
     m[15] = fma(B.FDa[1][0], a.D[0], B.FDa[1][1] * a.D[1]);
     m[6] = fma(B.FDd[0][0], a.D[2], B.FDd[0][1] * a.D[3]);
@@ -181,7 +185,7 @@ __host__ __device__ __forceinline__ void inverse_nc(const Blocks& B, const doubl
     for (int g = 0; g < 4; ++g) {
         S[g] = fma(B.I0[g][2], w[4], B.I0[g][3] * w[13]);
         X[g] = fma(B.IX[g][1], w[7], fma(B.IX[g][2], w[9], B.IX[g][3] * w[11]));
-        Y[g] = fma(B.IY[g][1], w[8], fma(B.IY[g][2], w[10], B.IY[g][3] * w[12]));
+        Y[g] = fma(B.IX[g][1], w[8], fma(B.IX[g][2], w[10], -B.IX[g][3] * w[12]));
     }
     D[0] = fma(B.IDa[0][0], w[5], B.IDa[0][1] * w[15]);
     D[1] = fma(B.IDa[1][0], w[5], B.IDa[1][1] * w[15]);
@@ -201,7 +205,7 @@ __host__ __device__ __forceinline__ void inverse_full(const Blocks& B, const dou
     for (int g = 0; g < 4; ++g) {
         S[g] = fma(B.I0[g][0], w[0], fma(B.I0[g][1], w[3], fma(B.I0[g][2], w[4], B.I0[g][3] * w[13])));
         X[g] = fma(B.IX[g][0], w[1], fma(B.IX[g][1], w[7], fma(B.IX[g][2], w[9], B.IX[g][3] * w[11])));
-        Y[g] = fma(B.IY[g][0], w[2], fma(B.IY[g][1], w[8], fma(B.IY[g][2], w[10], B.IY[g][3] * w[12])));
+        Y[g] = fma(B.IX[g][0], w[2], fma(B.IX[g][1], w[8], fma(B.IX[g][2], w[10], -B.IX[g][3] * w[12])));
     }
     D[0] = fma(B.IDa[0][0], w[5], B.IDa[0][1] * w[15]);
     D[1] = fma(B.IDa[1][0], w[5], B.IDa[1][1] * w[15]);
@@ -231,7 +235,7 @@ __device__ __forceinline__ void macro_of(const Blocks& B, double inv_b, const do
     Sums a = all_sums(f);
     rho = (a.S[0] + a.S[1]) + (a.S[2] + a.S[3]);
     double jx = dot4(B.FX[0], a.X);
-    double jy = dot4(B.FY[0], a.Y);
+    double jy = dot4(B.FX[0], a.Y);
     double e = dot4(B.F0[1], a.S);
     double ir = 1.0 / rho;
     ux = jx * ir;
@@ -247,13 +251,16 @@ __device__ __forceinline__ void velocity_of(const Blocks& B, const double* f, do
     double rho = (a.S[0] + a.S[1]) + (a.S[2] + a.S[3]);
     double ir = 1.0 / rho;
     ux = dot4(B.FX[0], a.X) * ir;
-    uy = dot4(B.FY[0], a.Y) * ir;
+    uy = dot4(B.FX[0], a.Y) * ir;
 }
 
 // ---------------------------------------------------------------------------
-// Limited jump psi(theta) * dn with theta = up / dn, in division-free form
-// (equal to the printed piecewise limiter wherever theta is defined; zero
-// when the downstream jump vanishes).
+// Limited jump psi(theta) * dn with theta = up / dn, in division-free and
+// branch-free form, equal to the printed piecewise limiter wherever theta is
+// defined and zero when the downstream jump vanishes:
+//   MC:     (sgn up + sgn dn) / 2 * min(2|up|, 2|dn|, |up + dn| / 2)
+//   minmod: (sgn up + sgn dn) / 2 * min(|up|, |dn|)
+// (opposite signs give zero; a zero jump makes the minimum zero).
 template <int LIM, typename R>
 __device__ __forceinline__ R limited(R up, R dn)
 {
@@ -262,14 +269,12 @@ __device__ __forceinline__ R limited(R up, R dn)
     } else if constexpr (LIM == 3) {    // first-order upwind
         return R(0);
     } else {
-        R au = fabs(up), ad = fabs(dn);
-        bool same = (up > R(0)) ? (dn > R(0)) : ((up < R(0)) && (dn < R(0)));
-        R m;
-        if constexpr (LIM == 0)         // MC: min(2|a|, (|a| + |d|) / 2, 2|d|)
-            m = fmin(R(2) * fmin(au, ad), R(0.5) * (au + ad));
-        else                            // minmod
-            m = fmin(au, ad);
-        return same ? copysign(m, dn) : R(0);
+        const R h = R(0.5) * (copysign(R(1), up) + copysign(R(1), dn));
+        const R au = fabs(up), ad = fabs(dn);
+        if constexpr (LIM == 0)
+            return h * fmin(R(2) * fmin(au, ad), R(0.5) * fabs(up + dn));
+        else
+            return h * fmin(au, ad);
     }
 }
 

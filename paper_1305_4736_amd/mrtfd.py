@@ -14,7 +14,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libmrtfd.so")
+# MRTFD_LIBRARY selects another build of the same library (e.g. a tuning variant)
+LIB_PATH = os.environ.get("MRTFD_LIBRARY") or os.path.join(_HERE, "libmrtfd.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(
