@@ -148,6 +148,68 @@ const char* mrtfd_last_error(void);
  * factored form (per-group angular sums times small blocks), for checks. */
 int mrtfd_constants(double eta0, double* M, double* Minv);
 
+/* ------------------------------------------------------------------------
+ * Batched form: many independent instances (different grids, states,
+ * rates, b and boundaries; one precision and one limiter per batch) advance
+ * together, one persistent launch per tile-shape class per step.  The
+ * per-instance arithmetic is the one above, so a slot's result does not
+ * depend on the other slots.  Slots own their device state (allocated from
+ * the stream-ordered pool on the batch's stream) and a step budget; slots
+ * that have used their budget stop stepping and stay readable until
+ * removed.  Slot numbers are reused after mrtfd_batch_remove.
+ * ------------------------------------------------------------------------ */
+typedef struct mrtfd_batch_s* mrtfd_batch_t;
+
+/* capacity slots (1 .. 65536); precision MRTFD_FP64 / MRTFD_FP32_STORAGE;
+ * limiter MRTFD_LIM_*; hip_stream a hipStream_t (NULL = null stream). */
+int mrtfd_batch_create(int capacity, int precision, int limiter, void* hip_stream, mrtfd_batch_t* out);
+int mrtfd_batch_destroy(mrtfd_batch_t b);
+
+/* Validate p (its precision and limiter must be the batch's), allocate the
+ * slot's state, initialise it to f^eq(rho, u, T) (Sec. IV-A) and give it a
+ * budget of nsteps steps (nsteps < 0: unlimited).  Fails with MRTFD_ENOMEM
+ * when no slot is free or the device allocation fails.  *slot receives the
+ * slot number. */
+int mrtfd_batch_add(mrtfd_batch_t b, const mrtfd_params* p, const double* rho, const double* ux,
+                    const double* uy, const double* T, int on_device, long nsteps, int* slot);
+int mrtfd_batch_remove(mrtfd_batch_t b, int slot);
+
+/* New budget for a slot, counted from now (nsteps < 0: unlimited). */
+int mrtfd_batch_set_steps(mrtfd_batch_t b, int slot, long nsteps);
+
+/* nsteps launches; each advances every slot that still has budget by one
+ * step.  Asynchronous on the batch's stream.  The timed form synchronises
+ * and reports the device time of those launches (HIP events). */
+int mrtfd_batch_step(mrtfd_batch_t b, long nsteps);
+int mrtfd_batch_step_timed(mrtfd_batch_t b, long nsteps, double* elapsed_ms);
+
+/* Steps a slot has taken since it was added or its state set, and the steps
+ * left in its budget (-1: unlimited). */
+long mrtfd_batch_steps_done(mrtfd_batch_t b, int slot);
+int mrtfd_batch_remaining(mrtfd_batch_t b, int slot, long* remaining);
+
+/* Per-slot outputs and checkpoint, as the single-instance calls. */
+int mrtfd_batch_macros(mrtfd_batch_t b, int slot, double* rho, double* ux, double* uy, double* T,
+                       int on_device);
+int mrtfd_batch_get_f(mrtfd_batch_t b, int slot, double* f, int on_device);
+int mrtfd_batch_set_f(mrtfd_batch_t b, int slot, const double* f, int on_device);
+
+/* Synchronise; flags[capacity] (may be NULL) receives 1 for every slot with
+ * a node at rho <= 0, T <= 0 or NaN since the last check, and the call
+ * returns MRTFD_ENONFINITE if any (flags are then cleared). */
+int mrtfd_batch_status(mrtfd_batch_t b, int* flags);
+int mrtfd_batch_sync(mrtfd_batch_t b);
+
+/* Tile shape chosen for a slot (nodes per block along x and y). */
+int mrtfd_batch_shape(mrtfd_batch_t b, int slot, int* txw, int* byr);
+
+/* Autotuner: measure the device time per tile of each tile shape (32 x 8,
+ * 64 x 4, 128 x 2, and 256 x 1 for one-row instances) on calibration
+ * instances, write them to cost_per_tile_us[4] (may be NULL), and give every
+ * slot the shape with the smallest tiles x cost.  Slot states are
+ * untouched; later additions use the measured costs. */
+int mrtfd_batch_autotune(mrtfd_batch_t b, double* cost_per_tile_us);
+
 #ifdef __cplusplus
 }
 #endif

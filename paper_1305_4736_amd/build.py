@@ -2,7 +2,7 @@
 
     python -m paper_1305_4736_amd.build
 
-compiles paper_1305_4736_amd/csrc/*.hip with hipcc for gfx950 into
+compiles paper_1305_4736_amd/csrc/mrtfd.hip and mrtfd_batch.hip with hipcc for gfx950 into
 paper_1305_4736_amd/libmrtfd.so.  Packed FP32 instructions are disabled for
 the device code (``-Xclang -target-feature -Xclang -packed-fp32-ops``).
 """
@@ -14,7 +14,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = os.path.join(HERE, "csrc", "mrtfd.hip")
+SRCS = [os.path.join(HERE, "csrc", n) for n in ("mrtfd.hip", "mrtfd_batch.hip")]
 LIB = os.path.join(HERE, "libmrtfd.so")
 HEADERS = [os.path.join(HERE, "csrc", n) for n in ("mrtfd_device.h", "mrtfd_consts.h")] + [
     os.path.join(ROOT, "include", "mrtfd.h")]
@@ -28,7 +28,7 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}",
 def build(verbose: bool = False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc, *FLAGS, "-o", tmp, SRC]
+    cmd = [hipcc, *FLAGS, "-o", tmp, *[s for s in SRCS if os.path.exists(s)]]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -1,0 +1,618 @@
+// mrtfd_batch.hip -- batched entry points of the C ABI (include/mrtfd.h):
+// many independent MRT-FD instances of different sizes, states and
+// parameters advance together, one persistent launch per tile-shape class
+// and step.
+//
+// Each occupied slot owns its parameters, its device state (two ping-pong
+// buffers from the stream-ordered pool allocator) and a step budget.  The
+// kernels find a slot's current buffer from the batch launch counter, so
+// adding, finishing or removing a slot only rewrites that slot's descriptor
+// and the work lists (stream-ordered copies), never the state of the others:
+// a slot's result does not depend on which other slots share its launches.
+//
+// Tile shapes (all 256 threads): 32 x 8, 64 x 4, 128 x 2, and 256 x 1 rows
+// for one-row instances.  Each slot gets the shape with the smallest
+// estimated cost (tiles x cost per tile); mrtfd_batch_autotune measures the
+// cost per tile of every shape on calibration grids and reassigns.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <new>
+#include <vector>
+
+#include "mrtfd_host.h"
+
+using namespace mrtfd;
+
+namespace {
+
+constexpr int NSHAPE = 4;
+struct ShapeDef {
+    int txw, byr;
+    bool flat;
+};
+constexpr ShapeDef SHAPES[NSHAPE] = {{32, 8, false}, {64, 4, false}, {128, 2, false}, {256, 1, true}};
+
+bool shape_fits(const mrtfd_params& p, int s)
+{
+    if (!SHAPES[s].flat) return true;
+    // one row whose y ghosts copy the row
+    return p.ny == 1 && (p.bc[2].kind == BC_PERIODIC || p.bc[2].kind == BC_OUTFLOW) &&
+           (p.bc[3].kind == BC_PERIODIC || p.bc[3].kind == BC_OUTFLOW);
+}
+
+long tiles_of(const mrtfd_params& p, int s)
+{
+    const int ex = p.nx - (p.bc[0].kind == BC_WALL) - (p.bc[1].kind == BC_WALL);
+    const int ey = p.ny - (p.bc[2].kind == BC_WALL) - (p.bc[3].kind == BC_WALL);
+    return (long)((ex + SHAPES[s].txw - 1) / SHAPES[s].txw) * ((ey + SHAPES[s].byr - 1) / SHAPES[s].byr);
+}
+
+}  // namespace
+
+struct mrtfd_batch_s {
+    int capacity, precision, limiter;
+    hipStream_t stream;
+    std::vector<BatchSlot> slot;        // host mirror of the device descriptors
+    std::vector<mrtfd_params> prm;
+    std::vector<Layout> lay;
+    std::vector<Blocks> blk;
+    std::vector<int> used, shape;
+    BatchSlot* d_slot;
+    Blocks* d_blocks;
+    int* d_flags;
+    int* d_lists;                       // NSHAPE x (capacity + 1) prefixes, then NSHAPE x capacity slot lists, then walls
+    int nlist[NSHAPE], nwall;
+    bool dirty;
+    long L;
+    double cost[NSHAPE];
+    double* staging;
+    size_t staging_bytes;
+    hipEvent_t ev0, ev1;
+    int max_blocks;
+};
+
+namespace {
+
+int* prefix_dev(mrtfd_batch_s* B, int s) { return B->d_lists + s * (B->capacity + 1); }
+int* list_dev(mrtfd_batch_s* B, int s) { return B->d_lists + NSHAPE * (B->capacity + 1) + s * B->capacity; }
+int* wall_dev(mrtfd_batch_s* B) { return B->d_lists + NSHAPE * (B->capacity + 1) + NSHAPE * B->capacity; }
+
+int check_slot(mrtfd_batch_s* B, int k)
+{
+    if (!B) return fail(MRTFD_EINVAL, "NULL batch");
+    if (k < 0 || k >= B->capacity || !B->used[k]) return fail(MRTFD_EINVAL, "slot %d is not occupied", k);
+    return MRTFD_OK;
+}
+
+int pick_shape(const mrtfd_batch_s* B, const mrtfd_params& p)
+{
+    int best = 0;
+    double best_cost = 1e300;
+    for (int s = 0; s < NSHAPE; ++s) {
+        if (!shape_fits(p, s)) continue;
+        const double c = (double)tiles_of(p, s) * B->cost[s];
+        if (c < best_cost) {
+            best_cost = c;
+            best = s;
+        }
+    }
+    return best;
+}
+
+void set_args(mrtfd_batch_s* B, int k)
+{
+    const ShapeDef& sd = SHAPES[B->shape[k]];
+    B->slot[k].a = make_args(B->prm[k], B->lay[k], B->blk[k], B->d_blocks + k, B->d_flags + k, sd.txw, sd.byr, 1 << 20);
+}
+
+int upload_slot(mrtfd_batch_s* B, int k)
+{
+    HIPCHK(hipMemcpyAsync(B->d_slot + k, &B->slot[k], sizeof(BatchSlot), hipMemcpyHostToDevice, B->stream));
+    return MRTFD_OK;
+}
+
+// Rebuild the per-shape work lists over slots that still step.
+int rebuild_lists(mrtfd_batch_s* B)
+{
+    std::vector<int> host(NSHAPE * (B->capacity + 1) + NSHAPE * B->capacity + B->capacity, 0);
+    B->nwall = 0;
+    for (int s = 0; s < NSHAPE; ++s) {
+        int n = 0, acc = 0;
+        int* pre = host.data() + s * (B->capacity + 1);
+        int* lst = host.data() + NSHAPE * (B->capacity + 1) + s * B->capacity;
+        for (int k = 0; k < B->capacity; ++k) {
+            if (!B->used[k] || B->shape[k] != s || B->L >= B->slot[k].stop) continue;
+            pre[n] = acc;
+            lst[n] = k;
+            acc += B->slot[k].a.ntx * B->slot[k].a.nty;
+            ++n;
+        }
+        pre[n] = acc;
+        B->nlist[s] = n;
+    }
+    int* wl = host.data() + NSHAPE * (B->capacity + 1) + NSHAPE * B->capacity;
+    for (int k = 0; k < B->capacity; ++k) {
+        if (!B->used[k] || B->L >= B->slot[k].stop) continue;
+        const mrtfd_params& p = B->prm[k];
+        bool walls = false;
+        for (int q = 0; q < 4; ++q) walls |= (p.bc[q].kind == BC_WALL);
+        if (walls) wl[B->nwall++] = k;
+    }
+    HIPCHK(hipMemcpyAsync(B->d_lists, host.data(), host.size() * sizeof(int), hipMemcpyHostToDevice, B->stream));
+    B->dirty = false;
+    return MRTFD_OK;
+}
+
+template <int LIM, typename T>
+int launch_shape(mrtfd_batch_s* B, int s, long items)
+{
+    const int grid = (int)std::min<long>(items, B->max_blocks);
+    const int* pre = prefix_dev(B, s);
+    const int* lst = list_dev(B, s);
+    const int n = B->nlist[s];
+    switch (s) {
+    case 0: hipLaunchKernelGGL((k_step_batch<LIM, T, 32, 8, false>), dim3(grid), dim3(256), 0, B->stream, B->d_slot, pre, lst, n, B->L); break;
+    case 1: hipLaunchKernelGGL((k_step_batch<LIM, T, 64, 4, false>), dim3(grid), dim3(256), 0, B->stream, B->d_slot, pre, lst, n, B->L); break;
+    case 2: hipLaunchKernelGGL((k_step_batch<LIM, T, 128, 2, false>), dim3(grid), dim3(256), 0, B->stream, B->d_slot, pre, lst, n, B->L); break;
+    default: hipLaunchKernelGGL((k_step_batch<LIM, T, 256, 1, true>), dim3(grid), dim3(256), 0, B->stream, B->d_slot, pre, lst, n, B->L); break;
+    }
+    HIPCHK(hipGetLastError());
+    return MRTFD_OK;
+}
+
+template <typename T>
+int launch_step_batch_t(mrtfd_batch_s* B)
+{
+    if (B->dirty) {
+        int rc = rebuild_lists(B);
+        if (rc) return rc;
+    }
+    for (int s = 0; s < NSHAPE; ++s) {
+        if (!B->nlist[s]) continue;
+        long items = 0;
+        for (int k = 0; k < B->capacity; ++k)
+            if (B->used[k] && B->shape[k] == s && B->L < B->slot[k].stop) items += (long)B->slot[k].a.ntx * B->slot[k].a.nty;
+        int rc = 0;
+        switch (B->limiter) {
+        case 0: rc = launch_shape<0, T>(B, s, items); break;
+        case 1: rc = launch_shape<1, T>(B, s, items); break;
+        case 2: rc = launch_shape<2, T>(B, s, items); break;
+        default: rc = launch_shape<3, T>(B, s, items); break;
+        }
+        if (rc) return rc;
+    }
+    if (B->nwall) {
+        hipLaunchKernelGGL((k_wall_batch<T>), dim3(B->nwall), dim3(256), 0, B->stream, B->d_slot, wall_dev(B), B->L);
+        HIPCHK(hipGetLastError());
+    }
+    B->L += 1;
+    // slots whose budget just ran out leave the work lists
+    for (int k = 0; k < B->capacity; ++k)
+        if (B->used[k] && B->slot[k].stop == B->L) B->dirty = true;
+    return MRTFD_OK;
+}
+
+int launch_step_batch(mrtfd_batch_s* B)
+{
+    return (B->precision == MRTFD_FP32_STORAGE) ? launch_step_batch_t<float>(B) : launch_step_batch_t<double>(B);
+}
+
+int ensure_staging(mrtfd_batch_s* B, size_t bytes)
+{
+    if (B->staging_bytes >= bytes) return MRTFD_OK;
+    if (B->staging) {
+        HIPCHK(hipStreamSynchronize(B->stream));
+        HIPCHK(hipFree(B->staging));
+        B->staging = nullptr;
+        B->staging_bytes = 0;
+    }
+    if (hipMalloc(&B->staging, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(MRTFD_ENOMEM, "cannot allocate %zu bytes of staging", bytes);
+    }
+    B->staging_bytes = bytes;
+    return MRTFD_OK;
+}
+
+// Buffer holding the slot's current state.
+int current_buffer(const mrtfd_batch_s* B, int k)
+{
+    const long done = std::min(B->L, B->slot[k].stop) - B->slot[k].start;
+    return (int)(done & 1);
+}
+
+template <typename T>
+int init_slot_t(mrtfd_batch_s* B, int k, const double* const* src, const double* fsrc)
+{
+    const StepArgs& a = B->slot[k].a;
+    const mrtfd_params& p = B->prm[k];
+    T* f = (T*)B->slot[k].buf[0];
+    dim3 grid((p.nx + 63) / 64, (p.ny + 3) / 4), block(64, 4);
+    if (fsrc) hipLaunchKernelGGL((k_scatter<T>), grid, block, 0, B->stream, f, fsrc, a);
+    else hipLaunchKernelGGL((k_init<T>), grid, block, 0, B->stream, f, src[0], src[1], src[2], src[3], a);
+    HIPCHK(hipGetLastError());
+    for (int axis = 0; axis < 2; ++axis) {
+        const int n = 2 * ((axis == 0) ? p.ny : p.nx);
+        hipLaunchKernelGGL((k_fill<T>), dim3((n + 127) / 128), dim3(128), 0, B->stream, f, a, axis, 0);
+        HIPCHK(hipGetLastError());
+    }
+    HIPCHK(hipMemcpyAsync(B->slot[k].buf[1], f, B->lay[k].buf_bytes, hipMemcpyDeviceToDevice, B->stream));
+    HIPCHK(hipMemsetAsync(B->d_flags + k, 0, sizeof(int), B->stream));
+    return MRTFD_OK;
+}
+
+int init_slot(mrtfd_batch_s* B, int k, const double* const* src, const double* fsrc)
+{
+    return (B->precision == MRTFD_FP32_STORAGE) ? init_slot_t<float>(B, k, src, fsrc) : init_slot_t<double>(B, k, src, fsrc);
+}
+
+}  // namespace
+
+extern "C" {
+
+int mrtfd_batch_create(int capacity, int precision, int limiter, void* hip_stream, mrtfd_batch_t* out)
+{
+    if (!out) return fail(MRTFD_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (capacity < 1 || capacity > 65536) return fail(MRTFD_EINVAL, "capacity %d out of range [1, 65536]", capacity);
+    if (precision != MRTFD_FP64 && precision != MRTFD_FP32_STORAGE) return fail(MRTFD_EINVAL, "unknown precision");
+    if (limiter < 0 || limiter > 3) return fail(MRTFD_EINVAL, "unknown limiter");
+    mrtfd_batch_s* B = new (std::nothrow) mrtfd_batch_s();
+    if (!B) return fail(MRTFD_ENOMEM, "host allocation failed");
+    B->capacity = capacity;
+    B->precision = precision;
+    B->limiter = limiter;
+    B->stream = (hipStream_t)hip_stream;
+    B->slot.resize(capacity);
+    B->prm.resize(capacity);
+    B->lay.resize(capacity);
+    B->blk.resize(capacity);
+    B->used.assign(capacity, 0);
+    B->shape.assign(capacity, 0);
+    for (int s = 0; s < NSHAPE; ++s) B->cost[s] = 1.0;   // until measured: fewest tiles wins
+    const size_t lists = (size_t)(NSHAPE * (capacity + 1) + NSHAPE * capacity + capacity) * sizeof(int);
+    if (hipMalloc(&B->d_slot, capacity * sizeof(BatchSlot)) != hipSuccess ||
+        hipMalloc(&B->d_blocks, capacity * sizeof(Blocks)) != hipSuccess ||
+        hipMalloc(&B->d_flags, capacity * sizeof(int)) != hipSuccess || hipMalloc(&B->d_lists, lists) != hipSuccess ||
+        hipEventCreate(&B->ev0) != hipSuccess || hipEventCreate(&B->ev1) != hipSuccess) {
+        (void)hipGetLastError();
+        mrtfd_batch_destroy(B);
+        return fail(MRTFD_ENOMEM, "batch set-up failed");
+    }
+    if (hipMemsetAsync(B->d_flags, 0, capacity * sizeof(int), B->stream) != hipSuccess ||
+        hipMemsetAsync(B->d_lists, 0, lists, B->stream) != hipSuccess) {
+        mrtfd_batch_destroy(B);
+        return fail(MRTFD_EDEVICE, "batch set-up failed");
+    }
+    int dev = 0, ncu = 256;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    B->max_blocks = 4 * ncu;   // persistent grid: a few resident blocks per CU
+    B->dirty = true;
+    *out = B;
+    return MRTFD_OK;
+}
+
+int mrtfd_batch_destroy(mrtfd_batch_t B)
+{
+    if (!B) return MRTFD_OK;
+    (void)hipStreamSynchronize(B->stream);
+    for (int k = 0; k < B->capacity; ++k)
+        if (B->used[k]) {
+            (void)hipFree(B->slot[k].buf[0]);
+            (void)hipFree(B->slot[k].buf[1]);
+        }
+    (void)hipFree(B->d_slot);
+    (void)hipFree(B->d_blocks);
+    (void)hipFree(B->d_flags);
+    (void)hipFree(B->d_lists);
+    if (B->staging) (void)hipFree(B->staging);
+    (void)hipEventDestroy(B->ev0);
+    (void)hipEventDestroy(B->ev1);
+    delete B;
+    return MRTFD_OK;
+}
+
+int mrtfd_batch_add(mrtfd_batch_t B, const mrtfd_params* p, const double* rho, const double* ux, const double* uy,
+                    const double* T, int on_device, long nsteps, int* slot_out)
+{
+    if (!B || !p || !slot_out || !rho || !ux || !uy || !T) return fail(MRTFD_EINVAL, "NULL argument");
+    *slot_out = -1;
+    int rc = validate(p);
+    if (rc) return rc;
+    if (p->precision != B->precision || p->limiter != B->limiter)
+        return fail(MRTFD_EINVAL, "instance precision / limiter differ from the batch's");
+    int k = 0;
+    while (k < B->capacity && B->used[k]) ++k;
+    if (k == B->capacity) return fail(MRTFD_ENOMEM, "all %d slots are occupied", B->capacity);
+    B->prm[k] = *p;
+    B->lay[k] = layout_of(*p);
+    if (!build_blocks(p->eta0, &B->blk[k])) return fail(MRTFD_EINVAL, "singular moment blocks for eta0 = %g", p->eta0);
+    void* b0 = nullptr;
+    void* b1 = nullptr;
+    if (hipMallocAsync(&b0, B->lay[k].buf_bytes, B->stream) != hipSuccess ||
+        hipMallocAsync(&b1, B->lay[k].buf_bytes, B->stream) != hipSuccess) {
+        (void)hipGetLastError();
+        if (b0) (void)hipFreeAsync(b0, B->stream);
+        return fail(MRTFD_ENOMEM, "cannot allocate 2 x %zu bytes for slot %d", B->lay[k].buf_bytes, k);
+    }
+    B->slot[k].buf[0] = b0;
+    B->slot[k].buf[1] = b1;
+    B->shape[k] = pick_shape(B, *p);
+    set_args(B, k);
+    B->slot[k].start = B->L;
+    B->slot[k].stop = (nsteps < 0) ? LONG_MAX : B->L + nsteps;
+    B->used[k] = 1;
+    rc = [&]() -> int {
+        HIPCHK(hipMemcpyAsync(B->d_blocks + k, &B->blk[k], sizeof(Blocks), hipMemcpyHostToDevice, B->stream));
+        int r = upload_slot(B, k);
+        if (r) return r;
+        const size_t n = (size_t)p->nx * p->ny;
+        const double* src[4] = {rho, ux, uy, T};
+        if (!on_device) {
+            r = ensure_staging(B, 4 * n * sizeof(double));
+            if (r) return r;
+            for (int q = 0; q < 4; ++q) {
+                HIPCHK(hipMemcpyAsync(B->staging + q * n, src[q], n * sizeof(double), hipMemcpyHostToDevice, B->stream));
+                src[q] = B->staging + q * n;
+            }
+        }
+        r = init_slot(B, k, src, nullptr);
+        if (r) return r;
+        if (!on_device) HIPCHK(hipStreamSynchronize(B->stream));
+        return MRTFD_OK;
+    }();
+    if (rc) {
+        (void)hipFreeAsync(b0, B->stream);
+        (void)hipFreeAsync(b1, B->stream);
+        B->used[k] = 0;
+        return rc;
+    }
+    B->dirty = true;
+    *slot_out = k;
+    return MRTFD_OK;
+}
+
+int mrtfd_batch_remove(mrtfd_batch_t B, int k)
+{
+    int rc = check_slot(B, k);
+    if (rc) return rc;
+    HIPCHK(hipFreeAsync(B->slot[k].buf[0], B->stream));
+    HIPCHK(hipFreeAsync(B->slot[k].buf[1], B->stream));
+    B->slot[k].buf[0] = B->slot[k].buf[1] = nullptr;
+    B->slot[k].stop = B->L;
+    B->used[k] = 0;
+    B->dirty = true;
+    return MRTFD_OK;
+}
+
+int mrtfd_batch_set_steps(mrtfd_batch_t B, int k, long nsteps)
+{
+    int rc = check_slot(B, k);
+    if (rc) return rc;
+    // keep the current buffer: restart the count at this launch
+    const int cur = current_buffer(B, k);
+    if (cur) {
+        std::swap(B->slot[k].buf[0], B->slot[k].buf[1]);
+    }
+    B->slot[k].start = B->L;
+    B->slot[k].stop = (nsteps < 0) ? LONG_MAX : B->L + nsteps;
+    rc = upload_slot(B, k);
+    if (rc) return rc;
+    B->dirty = true;
+    return MRTFD_OK;
+}
+
+int mrtfd_batch_step(mrtfd_batch_t B, long nsteps)
+{
+    if (!B) return fail(MRTFD_EINVAL, "NULL batch");
+    if (nsteps < 0) return fail(MRTFD_EINVAL, "nsteps < 0");
+    for (long s = 0; s < nsteps; ++s) {
+        int rc = launch_step_batch(B);
+        if (rc) return rc;
+    }
+    return MRTFD_OK;
+}
+
+int mrtfd_batch_step_timed(mrtfd_batch_t B, long nsteps, double* elapsed_ms)
+{
+    if (!B || !elapsed_ms) return fail(MRTFD_EINVAL, "NULL argument");
+    if (B->dirty) {
+        int rc = rebuild_lists(B);
+        if (rc) return rc;
+    }
+    HIPCHK(hipEventRecord(B->ev0, B->stream));
+    int rc = mrtfd_batch_step(B, nsteps);
+    if (rc) return rc;
+    HIPCHK(hipEventRecord(B->ev1, B->stream));
+    HIPCHK(hipEventSynchronize(B->ev1));
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, B->ev0, B->ev1));
+    *elapsed_ms = ms;
+    return MRTFD_OK;
+}
+
+long mrtfd_batch_steps_done(mrtfd_batch_t B, int k)
+{
+    if (check_slot(B, k)) return -1;
+    return std::min(B->L, B->slot[k].stop) - B->slot[k].start;
+}
+
+int mrtfd_batch_remaining(mrtfd_batch_t B, int k, long* remaining)
+{
+    int rc = check_slot(B, k);
+    if (rc) return rc;
+    if (!remaining) return fail(MRTFD_EINVAL, "NULL argument");
+    *remaining = (B->slot[k].stop == LONG_MAX) ? -1 : std::max(0L, B->slot[k].stop - B->L);
+    return MRTFD_OK;
+}
+
+int mrtfd_batch_macros(mrtfd_batch_t B, int k, double* rho, double* ux, double* uy, double* T, int on_device)
+{
+    int rc = check_slot(B, k);
+    if (rc) return rc;
+    const mrtfd_params& p = B->prm[k];
+    const size_t n = (size_t)p.nx * p.ny;
+    double* dst[4] = {rho, ux, uy, T};
+    if (!on_device) {
+        rc = ensure_staging(B, 4 * n * sizeof(double));
+        if (rc) return rc;
+        for (int q = 0; q < 4; ++q) dst[q] = dst[q] ? B->staging + q * n : nullptr;
+    }
+    const void* f = B->slot[k].buf[current_buffer(B, k)];
+    dim3 grid((p.nx + 63) / 64, (p.ny + 3) / 4), block(64, 4);
+    if (B->precision == MRTFD_FP32_STORAGE)
+        hipLaunchKernelGGL((k_macros<float>), grid, block, 0, B->stream, (const float*)f, dst[0], dst[1], dst[2], dst[3], B->slot[k].a);
+    else
+        hipLaunchKernelGGL((k_macros<double>), grid, block, 0, B->stream, (const double*)f, dst[0], dst[1], dst[2], dst[3], B->slot[k].a);
+    HIPCHK(hipGetLastError());
+    if (!on_device) {
+        double* host[4] = {rho, ux, uy, T};
+        for (int q = 0; q < 4; ++q)
+            if (host[q]) HIPCHK(hipMemcpyAsync(host[q], B->staging + q * n, n * sizeof(double), hipMemcpyDeviceToHost, B->stream));
+        HIPCHK(hipStreamSynchronize(B->stream));
+    }
+    return MRTFD_OK;
+}
+
+int mrtfd_batch_get_f(mrtfd_batch_t B, int k, double* f, int on_device)
+{
+    int rc = check_slot(B, k);
+    if (rc) return rc;
+    if (!f) return fail(MRTFD_EINVAL, "NULL argument");
+    const mrtfd_params& p = B->prm[k];
+    const size_t n = (size_t)p.nx * p.ny;
+    double* dst = f;
+    if (!on_device) {
+        rc = ensure_staging(B, NQ * n * sizeof(double));
+        if (rc) return rc;
+        dst = B->staging;
+    }
+    const void* src = B->slot[k].buf[current_buffer(B, k)];
+    dim3 grid((p.nx + 63) / 64, (p.ny + 3) / 4), block(64, 4);
+    if (B->precision == MRTFD_FP32_STORAGE)
+        hipLaunchKernelGGL((k_gather<float>), grid, block, 0, B->stream, (const float*)src, dst, B->slot[k].a);
+    else
+        hipLaunchKernelGGL((k_gather<double>), grid, block, 0, B->stream, (const double*)src, dst, B->slot[k].a);
+    HIPCHK(hipGetLastError());
+    if (!on_device) {
+        HIPCHK(hipMemcpyAsync(f, B->staging, NQ * n * sizeof(double), hipMemcpyDeviceToHost, B->stream));
+        HIPCHK(hipStreamSynchronize(B->stream));
+    }
+    return MRTFD_OK;
+}
+
+int mrtfd_batch_set_f(mrtfd_batch_t B, int k, const double* f, int on_device)
+{
+    int rc = check_slot(B, k);
+    if (rc) return rc;
+    if (!f) return fail(MRTFD_EINVAL, "NULL argument");
+    const mrtfd_params& p = B->prm[k];
+    const size_t n = (size_t)p.nx * p.ny;
+    const double* src = f;
+    if (!on_device) {
+        rc = ensure_staging(B, NQ * n * sizeof(double));
+        if (rc) return rc;
+        HIPCHK(hipMemcpyAsync(B->staging, f, NQ * n * sizeof(double), hipMemcpyHostToDevice, B->stream));
+        src = B->staging;
+    }
+    // the state restarts in buffer 0 with the remaining budget
+    const long remaining = (B->slot[k].stop == LONG_MAX) ? -1 : std::max(0L, B->slot[k].stop - B->L);
+    B->slot[k].start = B->L;
+    B->slot[k].stop = (remaining < 0) ? LONG_MAX : B->L + remaining;
+    rc = upload_slot(B, k);
+    if (rc) return rc;
+    rc = init_slot(B, k, nullptr, src);
+    if (rc) return rc;
+    if (!on_device) HIPCHK(hipStreamSynchronize(B->stream));
+    B->dirty = true;
+    return MRTFD_OK;
+}
+
+int mrtfd_batch_status(mrtfd_batch_t B, int* flags)
+{
+    if (!B) return fail(MRTFD_EINVAL, "NULL batch");
+    HIPCHK(hipStreamSynchronize(B->stream));
+    std::vector<int> h(B->capacity, 0);
+    HIPCHK(hipMemcpy(h.data(), B->d_flags, B->capacity * sizeof(int), hipMemcpyDeviceToHost));
+    int bad = 0;
+    for (int k = 0; k < B->capacity; ++k) {
+        if (flags) flags[k] = h[k];
+        bad += (h[k] != 0);
+    }
+    if (bad) {
+        HIPCHK(hipMemset(B->d_flags, 0, B->capacity * sizeof(int)));
+        return fail(MRTFD_ENONFINITE, "%d slot(s) reached rho <= 0, T <= 0 or NaN", bad);
+    }
+    return MRTFD_OK;
+}
+
+int mrtfd_batch_shape(mrtfd_batch_t B, int k, int* txw, int* byr)
+{
+    int rc = check_slot(B, k);
+    if (rc) return rc;
+    if (txw) *txw = SHAPES[B->shape[k]].txw;
+    if (byr) *byr = SHAPES[B->shape[k]].byr;
+    return MRTFD_OK;
+}
+
+// Measure the cost per tile of every shape on calibration instances (a 2-D
+// grid for the three 2-D shapes, a one-row grid for the row shape), then
+// give every occupied slot the cheapest shape.  Slot states are untouched.
+int mrtfd_batch_autotune(mrtfd_batch_t B, double* cost_per_tile_us)
+{
+    if (!B) return fail(MRTFD_EINVAL, "NULL batch");
+    HIPCHK(hipStreamSynchronize(B->stream));
+    for (int s = 0; s < NSHAPE; ++s) {
+        mrtfd_params p;
+        std::memset(&p, 0, sizeof(p));
+        p.nx = SHAPES[s].flat ? 262144 : 2048;
+        p.ny = SHAPES[s].flat ? 1 : 512;
+        p.dx = p.dy = 1.0 / 512;
+        p.dt = 0.05 * p.dx / 6.0;
+        p.eta0 = 2.5;
+        for (int q = 0; q < NQ; ++q) p.s[q] = 0.5 / p.dt;
+        p.b = 5.0;
+        p.limiter = B->limiter;
+        p.precision = B->precision;
+        p.energy_flux_correction = 1;
+        for (int q = 0; q < 4; ++q) p.bc[q] = mrtfd_bc{MRTFD_BC_PERIODIC, 1.0, 0.0, 0.0, 1.0};
+        mrtfd_batch_t C = nullptr;
+        int rc = mrtfd_batch_create(1, B->precision, B->limiter, B->stream, &C);
+        if (rc) return rc;
+        for (int q = 0; q < NSHAPE; ++q) C->cost[q] = (q == s) ? 1.0 : 1e30;   // force shape s
+        const size_t n = (size_t)p.nx * p.ny;
+        std::vector<double> one(n, 1.0), zero(n, 0.0);
+        int k = -1;
+        rc = mrtfd_batch_add(C, &p, one.data(), zero.data(), zero.data(), one.data(), 0, -1, &k);
+        double ms = 0.0;
+        if (!rc) rc = mrtfd_batch_step(C, 3);
+        if (!rc) rc = mrtfd_batch_step_timed(C, 20, &ms);
+        const long tiles = tiles_of(p, s);
+        mrtfd_batch_destroy(C);
+        if (rc) return rc;
+        B->cost[s] = 1e3 * ms / 20.0 / (double)tiles;   // microseconds per tile
+        if (cost_per_tile_us) cost_per_tile_us[s] = B->cost[s];
+    }
+    for (int k = 0; k < B->capacity; ++k) {
+        if (!B->used[k]) continue;
+        const int s = pick_shape(B, B->prm[k]);
+        if (s == B->shape[k]) continue;
+        B->shape[k] = s;
+        set_args(B, k);
+        int rc = upload_slot(B, k);
+        if (rc) return rc;
+    }
+    B->dirty = true;
+    return MRTFD_OK;
+}
+
+int mrtfd_batch_sync(mrtfd_batch_t B)
+{
+    if (!B) return fail(MRTFD_EINVAL, "NULL batch");
+    HIPCHK(hipStreamSynchronize(B->stream));
+    return MRTFD_OK;
+}
+
+}  // extern "C"

@@ -237,3 +237,150 @@ class Solver:
         p, dev, keep = _ptr(f, (16, self.ny, self.nx))
         _check(_lib.mrtfd_set_f(self._h, _vp(p), dev))
         return self
+
+
+# ----------------------------------------------------------------------------
+# Batched form
+
+_B = ctypes.c_void_p
+_lib.mrtfd_batch_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, ctypes.POINTER(_B)]
+_lib.mrtfd_batch_destroy.argtypes = [_B]
+_lib.mrtfd_batch_add.argtypes = [_B, ctypes.POINTER(_Params), _vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_long,
+                                 ctypes.POINTER(ctypes.c_int)]
+_lib.mrtfd_batch_remove.argtypes = [_B, ctypes.c_int]
+_lib.mrtfd_batch_set_steps.argtypes = [_B, ctypes.c_int, ctypes.c_long]
+_lib.mrtfd_batch_step.argtypes = [_B, ctypes.c_long]
+_lib.mrtfd_batch_step_timed.argtypes = [_B, ctypes.c_long, _dp]
+_lib.mrtfd_batch_steps_done.argtypes = [_B, ctypes.c_int]
+_lib.mrtfd_batch_steps_done.restype = ctypes.c_long
+_lib.mrtfd_batch_remaining.argtypes = [_B, ctypes.c_int, ctypes.POINTER(ctypes.c_long)]
+_lib.mrtfd_batch_macros.argtypes = [_B, ctypes.c_int, _vp, _vp, _vp, _vp, ctypes.c_int]
+_lib.mrtfd_batch_get_f.argtypes = [_B, ctypes.c_int, _vp, ctypes.c_int]
+_lib.mrtfd_batch_set_f.argtypes = [_B, ctypes.c_int, _vp, ctypes.c_int]
+_lib.mrtfd_batch_status.argtypes = [_B, ctypes.POINTER(ctypes.c_int)]
+_lib.mrtfd_batch_sync.argtypes = [_B]
+_lib.mrtfd_batch_shape.argtypes = [_B, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+_lib.mrtfd_batch_autotune.argtypes = [_B, _dp]
+
+
+class Batch:
+    """Many independent instances advanced together (one precision and one
+    limiter per batch)."""
+
+    def __init__(self, capacity: int, precision: str = "fp64", limiter: str = "mc", stream=None):
+        if stream is None:
+            stream = _default_stream()
+        elif hasattr(stream, "cuda_stream"):
+            stream = stream.cuda_stream
+        self.stream = int(stream)
+        self.capacity = int(capacity)
+        self.precision, self.limiter = precision, limiter
+        self._b = _B()
+        self._shapes = {}
+        _check(_lib.mrtfd_batch_create(self.capacity, PRECISIONS[precision], LIMITERS[limiter],
+                                       _vp(self.stream), ctypes.byref(self._b)))
+
+    def close(self):
+        if self._b:
+            _lib.mrtfd_batch_destroy(self._b)
+            self._b = _B()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def add(self, params: dict, rho, ux, uy, T, nsteps: int = -1) -> int:
+        p = dict(params, precision=self.precision, limiter=self.limiter)
+        cp = c_params(p)
+        shp = (int(p["ny"]), int(p["nx"]))
+        ptrs = [_ptr(a, shp) for a in (rho, ux, uy, T)]
+        dev = {q[1] for q in ptrs}
+        if len(dev) != 1:
+            raise ValueError("mix of host and device inputs")
+        slot = ctypes.c_int(-1)
+        _check(_lib.mrtfd_batch_add(self._b, ctypes.byref(cp), *[_vp(q[0]) for q in ptrs], dev.pop(),
+                                    int(nsteps), ctypes.byref(slot)))
+        self._shapes[slot.value] = shp
+        return slot.value
+
+    def remove(self, slot: int):
+        _check(_lib.mrtfd_batch_remove(self._b, int(slot)))
+        self._shapes.pop(slot, None)
+
+    def set_steps(self, slot: int, nsteps: int):
+        _check(_lib.mrtfd_batch_set_steps(self._b, int(slot), int(nsteps)))
+
+    def step(self, nsteps: int = 1):
+        _check(_lib.mrtfd_batch_step(self._b, int(nsteps)))
+        return self
+
+    def step_timed(self, nsteps: int) -> float:
+        ms = ctypes.c_double(0.0)
+        _check(_lib.mrtfd_batch_step_timed(self._b, int(nsteps), ctypes.byref(ms)))
+        return ms.value
+
+    def steps_done(self, slot: int) -> int:
+        return int(_lib.mrtfd_batch_steps_done(self._b, int(slot)))
+
+    def remaining(self, slot: int) -> int:
+        r = ctypes.c_long(0)
+        _check(_lib.mrtfd_batch_remaining(self._b, int(slot), ctypes.byref(r)))
+        return int(r.value)
+
+    def macros(self, slot: int, out=None):
+        shp = self._shapes[slot]
+        if out is None:
+            out = tuple(np.zeros(shp) for _ in range(4))
+        ptrs = [_ptr(a, shp, writable=True) for a in out]
+        dev = {q[1] for q in ptrs if q[2] is not None}
+        on_dev = dev.pop() if dev else 0
+        _check(_lib.mrtfd_batch_macros(self._b, int(slot), *[_vp(q[0]) if q[0] else None for q in ptrs], on_dev))
+        return out
+
+    def get_f(self, slot: int, out=None):
+        shp = (16,) + self._shapes[slot]
+        if out is None:
+            out = np.zeros(shp)
+        p, dev, _ = _ptr(out, shp, writable=True)
+        _check(_lib.mrtfd_batch_get_f(self._b, int(slot), _vp(p), dev))
+        return out
+
+    def set_f(self, slot: int, f):
+        p, dev, keep = _ptr(f, (16,) + self._shapes[slot])
+        _check(_lib.mrtfd_batch_set_f(self._b, int(slot), _vp(p), dev))
+
+    def status(self):
+        """Per-slot non-finite flags (numpy int array); raises NonFiniteError
+        (with .flags) if any slot was flagged since the last check."""
+        flags = np.zeros(self.capacity, dtype=np.int32)
+        rc = _lib.mrtfd_batch_status(self._b, flags.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
+        if rc == ENONFINITE:
+            err = NonFiniteError(rc, _lib.mrtfd_last_error().decode())
+            err.flags = flags
+            raise err
+        _check(rc)
+        return flags
+
+    def sync(self):
+        _check(_lib.mrtfd_batch_sync(self._b))
+        return self
+
+    def shape(self, slot: int):
+        tx, ty = ctypes.c_int(0), ctypes.c_int(0)
+        _check(_lib.mrtfd_batch_shape(self._b, int(slot), ctypes.byref(tx), ctypes.byref(ty)))
+        return tx.value, ty.value
+
+    def autotune(self):
+        """Measured device time per tile (microseconds) of the tile shapes
+        32x8, 64x4, 128x2, 256x1; every slot then gets its cheapest shape."""
+        c = np.zeros(4)
+        _check(_lib.mrtfd_batch_autotune(self._b, c.ctypes.data_as(_dp)))
+        return c

@@ -1,0 +1,156 @@
+"""GPU tests of the batched form: many instances of different sizes, states,
+rates and boundaries advance in shared persistent launches.
+
+* each slot matches the FP64 oracle (1e-11 FP64 storage, 2e-5 FP32);
+* each slot's result is the same alone and in the mix (bitwise), and the
+  same as the single-instance entry point;
+* per-slot step budgets, slots added and removed mid-run, the autotuner's
+  shape reassignment and a non-finite slot leave the other slots' results
+  unchanged.
+"""
+import numpy as np
+import pytest
+
+from parity import TOL, assert_parity
+from paper_1305_4736_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1305_4736_amd import mrtfd
+    return mrtfd
+
+
+P, E, O = W.bc("periodic"), W.bc("equilibrium", 1.1, 0.05, -0.02, 0.9), W.bc("outflow")
+
+
+def mixed_cases(limiter="mc"):
+    cs = [
+        W.riemann_1d((1.0, 0.1, 1.0), (0.3, 0.0, 0.4), 1.4, 300, ny=1, limiter=limiter, nsteps=0),
+        W.random_smooth(67, 13, seed=1, bcs=[P, P, P, P], limiter=limiter, jumps=True),
+        W.random_smooth(50, 20, seed=2, bcs=[E, O, P, P], limiter=limiter, jumps=True),
+        W.couette(pr=1.0, nx=4, ny=30, limiter=limiter),
+        W.random_smooth(1, 37, seed=3, bcs=[P, P, P, P], limiter=limiter),
+        W.riemann_1d((1.0, 0.0, 1.0), (0.5, 0.2, 0.5), 1.67, 200, ny=5, limiter=limiter, nsteps=0),
+        W.random_smooth(130, 70, seed=4, bcs=[O, O, O, O], limiter=limiter, jumps=True),
+        W.riemann_1d((2.0, 0.0, 2.0), (1.0, 0.0, 1.0), 1.2, 777, ny=1, limiter=limiter, nsteps=0),
+    ]
+    return cs
+
+
+def add_all(batch, cases, budgets=None):
+    slots = []
+    for k, c in enumerate(cases):
+        n = -1 if budgets is None else budgets[k]
+        slots.append(batch.add(c["params"], c["rho"], c["ux"], c["uy"], c["T"], nsteps=n))
+    return slots
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batch_matches_oracle(lib, orc, precision):
+    cases = mixed_cases()
+    n = 40
+    with lib.Batch(len(cases) + 3, precision=precision) as b:
+        slots = add_all(b, cases)
+        shapes = {b.shape(s) for s in slots}
+        assert (256, 1) in shapes          # one-row instances get the row tile
+        b.step(n)
+        b.status()
+        for c, s in zip(cases, slots):
+            mg = b.macros(s)
+            fo = orc.run(c["params"], c["rho"], c["ux"], c["uy"], c["T"], n)
+            mo = orc.macros(c["params"], fo)
+            gamma = (c["params"]["b"] + 2.0) / c["params"]["b"]
+            assert_parity(mg, mo, TOL[precision], gamma, f"slot {s} {c['name']}")
+            assert b.steps_done(s) == n
+
+
+def test_alone_equals_mix(lib):
+    cases = mixed_cases()
+    n = 30
+    with lib.Batch(len(cases)) as mix:
+        slots = add_all(mix, cases)
+        mix.step(n)
+        in_mix = [mix.get_f(s) for s in slots]
+    for c, fm in zip(cases, in_mix):
+        with lib.Batch(1) as alone:
+            s = alone.add(c["params"], c["rho"], c["ux"], c["uy"], c["T"])
+            alone.step(n)
+            assert np.array_equal(alone.get_f(s), fm), c["name"]
+        with lib.Solver(c["params"]) as single:
+            single.init(c["rho"], c["ux"], c["uy"], c["T"])
+            single.step(n)
+            assert np.array_equal(single.get_f(), fm), c["name"]
+
+
+def test_budgets_and_membership_changes(lib):
+    cases = mixed_cases()
+    budgets = [10, 25, -1, 5, 30, 0, 17, 12]
+    with lib.Batch(len(cases) + 2) as b:
+        slots = add_all(b, cases, budgets)
+        b.step(10)
+        # slot 0 has finished: remove it; a new instance joins with budget 20
+        b.remove(slots[0])
+        extra = W.random_smooth(45, 9, seed=9, bcs=[E, O, P, P], jumps=True)
+        s_new = b.add(extra["params"], extra["rho"], extra["ux"], extra["uy"], extra["T"], nsteps=20)
+        b.step(20)
+        done = {s: b.steps_done(s) for s in slots[1:]}
+        assert done[slots[1]] == 25 and done[slots[2]] == 30 and done[slots[3]] == 5
+        assert done[slots[4]] == 30 and done[slots[5]] == 0 and done[slots[6]] == 17
+        assert b.steps_done(s_new) == 20 and b.remaining(s_new) == 0 and b.remaining(slots[2]) == -1
+        for k in range(1, len(cases)):
+            c = cases[k]
+            with lib.Solver(c["params"]) as single:
+                single.init(c["rho"], c["ux"], c["uy"], c["T"])
+                single.step(done[slots[k]])
+                assert np.array_equal(single.get_f(), b.get_f(slots[k])), c["name"]
+        with lib.Solver(extra["params"]) as single:
+            single.init(extra["rho"], extra["ux"], extra["uy"], extra["T"])
+            single.step(20)
+            assert np.array_equal(single.get_f(), b.get_f(s_new))
+        # a new budget continues from the current state
+        b.set_steps(slots[1], 3)
+        b.step(5)
+        assert b.steps_done(slots[1]) == 3
+
+
+def test_autotune_keeps_results(lib):
+    cases = mixed_cases()
+    n = 12
+    with lib.Batch(len(cases)) as b1:
+        s1 = add_all(b1, cases)
+        b1.step(n)
+        ref = [b1.get_f(s) for s in s1]
+    with lib.Batch(len(cases)) as b2:
+        s2 = add_all(b2, cases)
+        costs = b2.autotune()
+        assert np.all(costs > 0) and np.all(np.isfinite(costs))
+        b2.step(n)
+        for r, s in zip(ref, s2):
+            assert np.array_equal(r, b2.get_f(s))
+
+
+def test_nonfinite_slot_is_isolated(lib):
+    cases = mixed_cases()[:4]
+    n = 8
+    with lib.Batch(4) as clean:
+        sc = add_all(clean, cases)
+        clean.step(n)
+        ref = [clean.get_f(s) for s in sc]
+    with lib.Batch(4) as b:
+        sb = add_all(b, cases)
+        f = b.get_f(sb[1])
+        f[:, 3, 10] = np.nan
+        b.set_f(sb[1], f)
+        b.step(n)
+        with pytest.raises(lib.NonFiniteError) as e:
+            b.status()
+        assert list(np.nonzero(e.value.flags)[0]) == [sb[1]]
+        for k in (0, 2, 3):
+            assert np.array_equal(ref[k], b.get_f(sb[k]))
+        b.status()      # cleared
