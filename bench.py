@@ -16,7 +16,15 @@ Printed: ONE JSON line with the contract fields plus
                   rocprofv3 counter summary when it matches the current kernel
   cpu_baseline -- the FP64 oracle on the host, on a bounded sample of the
                   same workload (a few full-grid steps)
-  fp32_storage -- the same workload with f stored and convected in FP32.
+  fp32_storage -- the same workload with f stored and convected in FP32
+  batched      -- 512 independent Riemann instances of uneven size in one
+                  batch (FP32 storage, autotuned tile shapes)
+  served       -- a Poisson stream of solve requests (Riemann quadrants and
+                  thermal Couette flows, 64..2048 per side, 200..5000 steps,
+                  FP32 / FP64) served with continuous batching: p50 / p99
+                  latency, offered and achieved node-updates/s; once at the
+                  specified 200 requests/s (overloaded) and once at a
+                  sustainable rate (drained).
 
 Options --pmc-copy-calibration and --no-cpu-baseline serve the profiling
 runs (see profiles/).
@@ -132,6 +140,53 @@ def cpu_baseline(log, nsteps=2):
                       f"(gcc -O2), {dt:.1f} s"}
 
 
+def run_batched(steps, warmup, log, n=512):
+    """512 independent Riemann instances (log-uniform Nx in [128, 4096], Ny in
+    [1, 256], seeded states) in one batch, FP32 storage, autotuned tiles."""
+    from paper_1305_4736_amd import mrtfd, workloads as W
+
+    cases, redraws = W.riemann_batch(n=n, precision="fp32")
+    nodes = sum(c["params"]["nx"] * c["params"]["ny"] for c in cases)
+    b = mrtfd.Batch(n, precision="fp32", limiter="mc")
+    for c in cases:
+        b.add(c["params"], c["rho"], c["ux"], c["uy"], c["T"])
+    costs = b.autotune()
+    shapes = {}
+    for k in range(n):
+        sh = "x".join(map(str, b.shape(k)))
+        shapes[sh] = shapes.get(sh, 0) + 1
+    b.step(warmup)
+    b.sync()
+    ms = b.step_timed(steps)
+    try:
+        b.status()
+        nonfinite = 0
+    except mrtfd.NonFiniteError as e:
+        nonfinite = int((e.flags != 0).sum())
+    b.close()
+    value = nodes * steps / (ms * 1e-3)
+    log(f"[bench] batched {n} instances, {nodes} nodes: {ms / steps:.4f} ms/step, {value:.4e} node-updates/s")
+    return {"workload": f"riemann_batch_{n}", "instances": n, "nodes": nodes, "precision": "fp32",
+            "limiter": "mc", "steps": steps, "ms_per_step": ms / steps, "value": value,
+            "unit": "node-updates/s", "screen_redraws": redraws, "nonfinite_instances": nonfinite,
+            "autotune_us_per_tile": {"32x8": costs[0], "64x4": costs[1], "128x2": costs[2], "256x1": costs[3]},
+            "tile_shapes": shapes}
+
+
+def run_served(rate, seconds, log, drain, label, steps_per_tick=50, capacity=4096, cap_bytes=None):
+    """Poisson stream of MRT-FD solve requests served with continuous batching."""
+    from paper_1305_4736_amd import serve, workloads as W
+
+    reqs = W.serve_stream(rate=rate, duration=seconds)
+    with serve.Server(capacity=capacity, steps_per_tick=steps_per_tick, max_resident_bytes=cap_bytes) as srv:
+        rep = srv.run(reqs, duration=seconds, drain=drain, log=log)
+    rep = {k: v for k, v in rep.items() if k != "results"}
+    rep.update({"label": label, "rate_per_s": rate, "arrival_window_s": seconds, "drained": drain})
+    log(f"[bench] served ({label}): {rep['completed']}/{rep['requests']} done, p50 {rep['p50_s']:.3f} s, "
+        f"p99 {rep['p99_s']:.3f} s, achieved {rep['achieved_node_updates_per_s']:.3e} node-updates/s")
+    return rep
+
+
 def copy_calibration(log, nbytes=1 << 30):
     """A plain device copy of known size, for scaling rocprofv3 byte counters."""
     import torch
@@ -153,6 +208,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--pmc-copy-calibration", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=8.0)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--sustainable-rate", type=float, default=15.0)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -185,6 +245,14 @@ def main():
         extra["fp32_storage"] = {"value": r32["value"], "ms_per_step": r32["ms_per_step"],
                                  "roofline_frac": rl32["frac"], "achieved_GBs": rl32["achieved"],
                                  "speedup_vs_fp64": r32["value"] / res["value"]}
+
+    if not args.no_batched:
+        extra["batched"] = run_batched(max(args.steps // 2, 20), 5, log)
+    if not args.no_serve:
+        extra["served"] = run_served(args.serve_rate, args.serve_seconds, log, drain=False,
+                                     label="offered load as specified (overloaded), stopped at the end of arrivals")
+        extra["served_sustainable"] = run_served(args.sustainable_rate, args.serve_seconds, log, drain=True,
+                                                 label="sustainable-rate run, drained")
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(log)
 

@@ -144,6 +144,10 @@ int mrtfd_destroy(mrtfd_t h);
  * owned by the library and valid until the next call on this thread. */
 const char* mrtfd_last_error(void);
 
+/* Free and total device memory of the current device in bytes (for
+ * admission by free HBM). */
+int mrtfd_device_memory(size_t* free_bytes, size_t* total_bytes);
+
 /* Host-only: the dense 16x16 M and M^-1 (row-major) the kernels use in their
  * factored form (per-group angular sums times small blocks), for checks. */
 int mrtfd_constants(double eta0, double* M, double* Minv);

@@ -374,6 +374,15 @@ int mrtfd_sync(mrtfd_t h)
 
 long mrtfd_steps_done(mrtfd_t h) { return h ? h->steps : -1; }
 
+int mrtfd_device_memory(size_t* free_bytes, size_t* total_bytes)
+{
+    size_t fr = 0, tot = 0;
+    HIPCHK(hipMemGetInfo(&fr, &tot));
+    if (free_bytes) *free_bytes = fr;
+    if (total_bytes) *total_bytes = tot;
+    return MRTFD_OK;
+}
+
 int mrtfd_constants(double eta0, double* M, double* Minv)
 {
     Blocks B;

@@ -104,6 +104,16 @@ def footprint(p: dict) -> int:
     return int(out.value)
 
 
+_lib.mrtfd_device_memory.argtypes = [ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]
+
+
+def device_memory():
+    """(free, total) device memory in bytes."""
+    fr, tot = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    _check(_lib.mrtfd_device_memory(ctypes.byref(fr), ctypes.byref(tot)))
+    return int(fr.value), int(tot.value)
+
+
 def constants(eta0: float = 2.5):
     """Dense M and M^-1 as the kernels apply them (host-only)."""
     M = np.zeros(256)

@@ -1,0 +1,169 @@
+"""Serving loop: continuous batching of MRT-FD solves on one GPU.
+
+Requests (a grid, an initial state, rates, boundaries, a step count and a
+storage precision) arrive over time.  The loop
+
+  * admits waiting requests (first come, first served) while device memory
+    and slots allow: a request's state (two padded 16-plane buffers) must fit
+    in the free HBM left after a reserve, under an optional cap on resident
+    bytes;
+  * keeps every admitted request's state resident as a slot of one of two
+    batches (FP32 storage, FP64), each slot with its own step budget;
+  * every tick, advances both batches by `steps_per_tick` launches: all
+    resident requests progress together, requests that arrived during the
+    previous tick join as soon as they are admitted, and a request that uses
+    up its budget stops stepping inside the tick;
+  * hands finished requests their (rho, u_x, u_y, T) on the host, records the
+    latency (arrival to result on the host) and frees their slot.
+
+All stepping runs in the library's batched kernels; this module only
+schedules.  The report gives p50 / p99 latency beside offered and achieved
+node-updates per second.
+"""
+from __future__ import annotations
+
+import collections
+import time
+
+import numpy as np
+
+from . import mrtfd
+from . import workloads as W
+
+
+class Server:
+    def __init__(self, capacity=2048, steps_per_tick=50, reserve_bytes=8 << 30, max_resident_bytes=None,
+                 limiter="mc", stream=None, keep_results=False):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.batches = {p: mrtfd.Batch(capacity, precision=p, limiter=limiter, stream=self.stream)
+                        for p in ("fp32", "fp64")}
+        self.capacity = capacity
+        self.k = int(steps_per_tick)
+        self.reserve = int(reserve_bytes)
+        self.cap_bytes = max_resident_bytes
+        self.keep_results = keep_results
+
+    def close(self):
+        for b in self.batches.values():
+            b.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def run(self, stream_reqs, duration=None, drain=True, log=None, realtime=True):
+        """Serve [(arrival_s, spec), ...] (sorted).  With realtime=False every
+        request arrives at t = 0.  Returns a report dict (and results if
+        keep_results)."""
+        torch = self.torch
+        reqs = sorted(stream_reqs, key=lambda r: r[0])
+        free0, total = mrtfd.device_memory()
+        budget = free0 - self.reserve
+        if self.cap_bytes is not None:
+            budget = min(budget, int(self.cap_bytes))
+        pending = collections.deque()
+        active = {}                 # (precision, slot) -> request record
+        resident = 0
+        nxt = 0
+        lat, done_nodeupd, results, admitted, ticks = [], 0.0, {}, 0, 0
+        max_resident, max_active = 0, 0
+        t0 = time.perf_counter()
+        while True:
+            now = time.perf_counter() - t0
+            while nxt < len(reqs) and (not realtime or reqs[nxt][0] <= now):
+                pending.append(nxt)
+                nxt += 1
+            # without draining, the run ends with the arrival window
+            stop_admitting = duration is not None and now >= duration and not drain
+            # admission: first come, first served within each precision, by free
+            # memory and free slots (a request whose batch is full is passed by
+            # requests of the other precision; memory is never overtaken)
+            if pending and not stop_admitting:
+                keep = collections.deque()
+                full = {p: sum(1 for k in active if k[0] == p) >= self.capacity for p in self.batches}
+                mem_blocked = False
+                while pending:
+                    i = pending.popleft()
+                    t_arr, spec = reqs[i]
+                    p = spec["params"]
+                    fp = mrtfd.footprint(p)
+                    if mem_blocked or full[p["precision"]] or resident + fp > budget:
+                        mem_blocked = mem_blocked or (resident + fp > budget and not full[p["precision"]])
+                        keep.append(i)
+                        continue
+                    b = self.batches[p["precision"]]
+                    fields = W.materialize(spec, torch, device=self.device)
+                    slot = b.add(p, *fields, nsteps=spec["nsteps"])
+                    active[(p["precision"], slot)] = {"i": i, "t": t_arr if realtime else 0.0, "fp": fp,
+                                                      "nodes": p["nx"] * p["ny"], "steps": spec["nsteps"]}
+                    resident += fp
+                    admitted += 1
+                    full[p["precision"]] = sum(1 for k in active if k[0] == p["precision"]) >= self.capacity
+                pending = keep
+            max_resident = max(max_resident, resident)
+            max_active = max(max_active, len(active))
+            if not active:
+                if nxt >= len(reqs) and not pending:
+                    break
+                if stop_admitting:
+                    break
+                if realtime and nxt < len(reqs):
+                    time.sleep(max(0.0, min(reqs[nxt][0] - (time.perf_counter() - t0), 0.002)))
+                continue
+            # one tick: every resident request advances (up to its budget)
+            for prec, b in self.batches.items():
+                if any(k[0] == prec for k in active):
+                    b.step(self.k)
+            for b in self.batches.values():
+                b.sync()
+            ticks += 1
+            # finished requests: results to the host, slots freed
+            finished = [key for key in active if self.batches[key[0]].remaining(key[1]) == 0]
+            for key in finished:
+                b = self.batches[key[0]]
+                rec = active.pop(key)
+                out = b.macros(key[1])
+                t_done = time.perf_counter() - t0
+                lat.append(t_done - rec["t"])
+                done_nodeupd += rec["nodes"] * rec["steps"]
+                if self.keep_results:
+                    results[rec["i"]] = out
+                b.remove(key[1])
+                resident -= rec["fp"]
+            if log and ticks % 20 == 0:
+                log(f"[serve] t={time.perf_counter() - t0:.1f}s active={len(active)} pending={len(pending)} "
+                    f"done={len(lat)}")
+            if stop_admitting:
+                break
+        elapsed = time.perf_counter() - t0
+        # work done by requests still resident (partial)
+        partial = sum(rec["nodes"] * self.batches[k[0]].steps_done(k[1]) for k, rec in active.items())
+        offered = sum(s["params"]["nx"] * s["params"]["ny"] * s["nsteps"] for _, s in reqs)
+        span = max(reqs[-1][0], 1e-9) if (reqs and realtime) else None
+        lat_a = np.array(lat) if lat else np.array([np.nan])
+        report = {
+            "requests": len(reqs), "admitted": admitted, "completed": len(lat),
+            "backlog": len(pending) + (len(reqs) - nxt), "resident_at_end": len(active),
+            "p50_s": float(np.percentile(lat_a, 50)), "p99_s": float(np.percentile(lat_a, 99)),
+            "mean_s": float(np.mean(lat_a)), "elapsed_s": elapsed, "ticks": ticks,
+            "steps_per_tick": self.k,
+            "achieved_node_updates_per_s": (done_nodeupd + partial) / elapsed,
+            "offered_node_updates_per_s": (offered / span) if span else None,
+            "max_resident_bytes": max_resident, "max_active": max_active,
+            "hbm_budget_bytes": budget,
+        }
+        nonfinite = 0
+        for b in self.batches.values():
+            try:
+                b.status()
+            except mrtfd.NonFiniteError as e:
+                nonfinite += int((e.flags != 0).sum())
+        report["nonfinite_slots"] = nonfinite
+        if self.keep_results:
+            report["results"] = results
+        return report

@@ -199,15 +199,24 @@ def paper_heavy_light(precision="fp64"):
 # --------------------------------------------------------------------------
 # Batched Riemann instances (512 by default)
 
-SCREEN_T_RATIO = 1.0 / 20.0
+# Stability envelope of the 16-velocity model with the rates below: states
+# are redrawn until both the pressure and the temperature ratios across the
+# problem stay within SCREEN_RATIO and every initial state is subsonic
+# (strong shocks, cold regions and supersonic states beyond these drive f
+# to negative temperatures within a few hundred steps, in the oracle and on
+# the GPU alike).
+SCREEN_RATIO = 5.0
+SCREEN_MACH = 1.0
 
 
 def riemann_batch(n=512, seed=13054736, nsteps=1000, precision="fp32"):
     """Independent two-state Riemann problems with log-uniform Nx in
     [128, 4096], Ny in [1, 256]; rho, p ~ U[0.1, 10], u ~ U[-0.5, 0.5],
-    gamma ~ U[1.1, 1.67]; states are redrawn while T_min / T_max < 1/20, then
-    rescaled to T_max = 1 (p /= T_ref, u /= sqrt(T_ref)).  dt = 0.01 dx,
-    dt*s = 0.5 (s_5..7) and 1 (the others)."""
+    gamma ~ U[1.1, 1.67]; states (and gamma) are redrawn while the pressure or
+    the temperature ratio exceeds SCREEN_RATIO or a side is supersonic, then
+    rescaled to T_max = 1
+    (p /= T_ref, u /= sqrt(T_ref)).  dt = 0.01 dx, dt*s = 0.5 (s_5..7) and 1
+    (the others)."""
     rng = np.random.default_rng(seed)
     cases = []
     redraws = 0
@@ -218,11 +227,13 @@ def riemann_batch(n=512, seed=13054736, nsteps=1000, precision="fp32"):
             rl, rr = rng.uniform(0.1, 10.0, 2)
             pl, pr = rng.uniform(0.1, 10.0, 2)
             ul, ur = rng.uniform(-0.5, 0.5, 2)
+            gamma = rng.uniform(1.1, 1.67)
             Tl, Tr = pl / rl, pr / rr
-            if min(Tl, Tr) / max(Tl, Tr) >= SCREEN_T_RATIO:
+            mach = max(abs(ul) / math.sqrt(gamma * Tl), abs(ur) / math.sqrt(gamma * Tr))
+            if (max(Tl, Tr) / min(Tl, Tr) <= SCREEN_RATIO and max(pl, pr) / min(pl, pr) <= SCREEN_RATIO
+                    and mach <= SCREEN_MACH):
                 break
             redraws += 1
-        gamma = rng.uniform(1.1, 1.67)
         Tref = max(Tl, Tr)
         pl, pr = pl / Tref, pr / Tref
         ul, ur = ul / math.sqrt(Tref), ur / math.sqrt(Tref)
@@ -237,16 +248,19 @@ def riemann_batch(n=512, seed=13054736, nsteps=1000, precision="fp32"):
 
 
 # --------------------------------------------------------------------------
-# Served stream of requests
+# Served stream of requests.  A request is a compact spec (parameters plus a
+# piecewise-constant initial state) so that its fields can be built where
+# they are used (numpy on the host, torch on the device).
 
-def _quadrant(rng, nx, ny, nsteps, precision, name):
+def _quadrant_spec(rng, nx, ny, nsteps, precision, name):
     while True:
         rho = rng.uniform(0.25, 4.0, 4)
         p = rng.uniform(0.25, 4.0, 4)
         u = rng.uniform(-0.3, 0.3, 4)
         v = rng.uniform(-0.3, 0.3, 4)
         T = p / rho
-        if T.min() / T.max() >= SCREEN_T_RATIO:
+        mach = (np.hypot(u, v) / np.sqrt(1.4 * T)).max()
+        if T.max() / T.min() <= SCREEN_RATIO and p.max() / p.min() <= SCREEN_RATIO and mach <= SCREEN_MACH:
             break
     Tref = T.max()
     T = T / Tref
@@ -255,35 +269,66 @@ def _quadrant(rng, nx, ny, nsteps, precision, name):
     dx, dy = 1.0 / nx, 1.0 / ny
     dt = 0.06 * min(dx, dy) / 6.0
     s = rates(1.0 / dt, 0.5 / dt, 1.0 / dt, 1.0 / dt)
-    x = cell_centres(nx, dx)[None, :]
-    y = cell_centres(ny, dy)[:, None]
-    q = (x >= 0.5).astype(int) + 2 * (y >= 0.5).astype(int)   # 0: SW, 1: SE, 2: NW, 3: NE
     bcs = [bc("outflow")] * 4
     prm = make_params(nx, ny, dx, dy, dt, s, b_of_gamma(gamma), bcs, precision=precision)
-    return _case(name, prm, rho[q], u[q], v[q], T[q], nsteps)
+    # quadrants 0: x < 1/2, y < 1/2; 1: x >= 1/2, y < 1/2; 2: x < 1/2, y >= 1/2; 3: both >= 1/2
+    return {"name": name, "kind": "quadrant", "params": prm, "nsteps": int(nsteps),
+            "quad": {"rho": rho.tolist(), "ux": u.tolist(), "uy": v.tolist(), "T": T.tolist()}}
+
+
+def _couette_spec(rng, nx, ny, nsteps, precision, name):
+    pr = rng.uniform(0.3, 3.0)
+    c = couette(pr=pr, gamma=1.4, nx=nx, ny=ny, precision=precision)
+    return {"name": name, "kind": "couette", "params": c["params"], "nsteps": int(nsteps),
+            "uniform": {"rho": 1.0, "ux": 0.0, "uy": 0.0, "T": 1.0}, "pr": pr}
 
 
 def serve_request(rng, k, log_lo=64, log_hi=2048):
+    """One request: half Riemann quadrant problems (outflow on all sides),
+    half thermal Couette flows with Pr ~ U[0.3, 3]; grid sides log-uniform in
+    [log_lo, log_hi]; steps ~ U{200..5000}; FP32 or FP64 storage."""
     kind = "quadrant" if rng.uniform() < 0.5 else "couette"
     nx = int(round(math.exp(rng.uniform(math.log(log_lo), math.log(log_hi)))))
     ny = int(round(math.exp(rng.uniform(math.log(log_lo), math.log(log_hi)))))
     nsteps = int(rng.integers(200, 5001))
     precision = "fp32" if rng.uniform() < 0.5 else "fp64"
     if kind == "quadrant":
-        return _quadrant(rng, nx, ny, nsteps, precision, f"req{k}_quadrant")
-    pr = rng.uniform(0.3, 3.0)
-    c = couette(pr=pr, gamma=1.4, nx=nx, ny=ny, precision=precision)
-    c["nsteps"] = nsteps
-    c["name"] = f"req{k}_couette"
-    return c
+        return _quadrant_spec(rng, nx, ny, nsteps, precision, f"req{k}_quadrant")
+    return _couette_spec(rng, nx, ny, nsteps, precision, f"req{k}_couette")
+
+
+def materialize(spec, xp=np, **kw):
+    """(rho, ux, uy, T) of a request spec as (ny, nx) float64 arrays of the
+    array module xp (numpy, or torch with device=... in kw)."""
+    prm = spec["params"]
+    nx, ny = prm["nx"], prm["ny"]
+    if "uniform" in spec:
+        return tuple(xp.full((ny, nx), float(spec["uniform"][k]), dtype=xp.float64, **kw)
+                     for k in ("rho", "ux", "uy", "T"))
+    xi = (xp.arange(nx, dtype=xp.float64, **kw) + 0.5) * prm["dx"]
+    yi = (xp.arange(ny, dtype=xp.float64, **kw) + 0.5) * prm["dy"]
+    east = (xi >= 0.5).reshape(1, nx)
+    north = (yi >= 0.5).reshape(ny, 1)
+    if xp is np:
+        qidx = east.astype(np.int64) + 2 * north.astype(np.int64)
+        table = lambda v: np.asarray(v, dtype=np.float64)
+    else:
+        qidx = east.long() + 2 * north.long()
+        table = lambda v: xp.tensor(v, dtype=xp.float64, **kw)
+    return tuple(table(spec["quad"][k])[qidx].contiguous() if xp is not np else table(spec["quad"][k])[qidx]
+                 for k in ("rho", "ux", "uy", "T"))
+
+
+def spec_case(spec):
+    """A request spec as an ordinary case dict (host fields)."""
+    r, u, v, T = materialize(spec)
+    return _case(spec["name"], spec["params"], r, u, v, T, spec["nsteps"])
 
 
 def serve_stream(rate=200.0, duration=60.0, seed=13054737, log_lo=64, log_hi=2048,
                  max_requests=None):
-    """Poisson arrivals; each request half Riemann-quadrant (outflow on all
-    sides), half thermal Couette with Pr ~ U[0.3, 3]; grids log-uniform in
-    [64, 2048] per axis, steps ~ U{200..5000}, FP32 or FP64 storage.
-    Returns a list of (arrival_time_s, case)."""
+    """Poisson arrivals at `rate` per second for `duration` seconds; returns a
+    list of (arrival_time_s, spec)."""
     rng = np.random.default_rng(seed)
     t = 0.0
     out = []
