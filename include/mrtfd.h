@@ -91,9 +91,11 @@ typedef struct mrtfd_s* mrtfd_t;
  * planes each, two ghost layers, rows padded to 128-byte lines) and bind the
  * handle to `hip_stream` (a hipStream_t; NULL = the null stream).  Rejects:
  * non-positive sizes or steps, unpaired periodic sides, walls on both axes,
- * grids too small for their walls, 6 dt (1/dx + 1/dy) > 2 (the unsplit
- * Courant bound on the fastest |v| = 6 velocities is checked per axis:
- * 6 dt / dx <= 1 and 6 dt / dy <= 1), dt * max(s_5..s_16) >= 2. */
+ * grids too small for their walls, a velocity whose unsplit Courant sum
+ * |v_x| dt / dx + |v_y| dt / dy exceeds 1 (for the axis groups this is
+ * |v| dt / min(dx, dy) <= 1, i.e. 6 dt / min(dx, dy) <= 1 for |v| = 6),
+ * negative rates, dt * max(s_5..s_16) >= 2, and the energy-flux correction
+ * with s_5 = 0. */
 int mrtfd_create(const mrtfd_params* p, void* hip_stream, mrtfd_t* out);
 
 /* Device bytes a handle with these parameters will hold (state buffers and
