@@ -43,7 +43,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "node-updates/s (D2V16 MRT-FD) + % HBM peak; p50/p99 served-solve latency"
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_step_shock_interface_4096x1024.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_march_shock_interface_4096x1024.json")
 
 
 def kernel_hash() -> str:
@@ -118,7 +118,7 @@ def roofline(res, precision):
             traffic = t["hbm_bytes_per_launch"]
     return {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "algorithmic_bytes_per_launch": bytes_launch, "kernel": "k_step",
+            "algorithmic_bytes_per_launch": bytes_launch, "kernel": "k_march",
             "avg_launch_ms": round(res["kernel_ms_avg"], 5)}
 
 

@@ -22,6 +22,9 @@ HEADERS = [os.path.join(HERE, "csrc", n) for n in ("mrtfd_device.h", "mrtfd_cons
 ARCH = os.environ.get("MRTFD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # a * b + c is fused only within one source expression, so every
+         # kernel that shares a device function rounds it the same way
+         "-ffp-contract=on",
          "-Wall", "-Wno-unused-function"]
 
 

@@ -1,8 +1,9 @@
 // mrtfd.hip -- C ABI (include/mrtfd.h) of the D2V16 MRT finite-difference
 // lattice-Boltzmann step (arXiv:1305.4736): single-instance entry points.
 //
-// One time step is ONE launch of the fused step kernel (mrtfd_kernels.h):
-// each thread owns one node and computes, from level n only, its moments
+// One time step is ONE launch of the fused step kernel (the row-marching
+// form of mrtfd_march.h): each node's new populations come, from level n
+// only, from its moments
 // and macroscopic state (Sec. II), the velocity of its four axis neighbours
 // (energy-flux correction, Sec. II), the equilibria (Appendix), the relaxed
 // residual mapped back to velocity space (Sec. III update eq.), the limited x
@@ -16,6 +17,7 @@
 #include <string>
 
 #include "mrtfd_host.h"
+#include "mrtfd_march.h"
 
 using namespace mrtfd;
 
@@ -38,8 +40,10 @@ struct mrtfd_s {
     StepArgs args;
     Blocks blocks;          // host copy
     Blocks* blocks_dev;     // device copy read by the kernels
+    StepArgs* args_dev;     // device copy of args (read by the row-marching step)
     bool ready;
     long steps;
+    long march_capacity;    // wavefronts of the step kernel resident at once
     hipEvent_t ev0, ev1;
 };
 
@@ -50,6 +54,31 @@ void fill_args(mrtfd_s* h)
     const bool f32 = h->p.precision == MRTFD_FP32_STORAGE;
     h->args = make_args(h->p, h->L, h->blocks, h->blocks_dev, h->flag, f32 ? STEP_TXW32 : STEP_TXW64,
                         f32 ? STEP_BYR32 : STEP_BYR64, STEP_BAND);
+    set_march(h->args, h->march_capacity);
+}
+
+template <typename T>
+const void* march_kernel(int limiter)
+{
+    switch (limiter) {
+    case 0: return (const void*)k_march<0, T>;
+    case 1: return (const void*)k_march<1, T>;
+    case 2: return (const void*)k_march<2, T>;
+    default: return (const void*)k_march<3, T>;
+    }
+}
+
+// Wavefronts of the step kernel that the device holds at once.
+int query_march_capacity(mrtfd_s* h)
+{
+    const void* k = (h->p.precision == MRTFD_FP32_STORAGE) ? march_kernel<float>(h->p.limiter)
+                                                            : march_kernel<double>(h->p.limiter);
+    int dev = 0, cus = 0, nb = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, MW * MWPB, 0));
+    h->march_capacity = (long)std::max(nb, 1) * MWPB * std::max(cus, 1);
+    return MRTFD_OK;
 }
 
 dim3 node_grid(int nx, int ny) { return dim3((nx + BX - 1) / BX, (ny + BY - 1) / BY); }
@@ -79,13 +108,24 @@ int launch_step_t(mrtfd_s* h)
     T* fout = (T*)h->buf[1 - h->cur];
     const int ex = a.x1 - a.x0, ey = a.y1 - a.y0;
     if (ex > 0 && ey > 0) {
-        constexpr int TXW = TileOf<T>::TXW, BYR = TileOf<T>::BYR;
-        dim3 grid(8 * a.per_xcd), block(TXW * BYR);
-        switch (h->p.limiter) {
-        case 0: hipLaunchKernelGGL((k_step<0, T, TXW, BYR>), grid, block, 0, h->stream, fin, fout, a); break;
-        case 1: hipLaunchKernelGGL((k_step<1, T, TXW, BYR>), grid, block, 0, h->stream, fin, fout, a); break;
-        case 2: hipLaunchKernelGGL((k_step<2, T, TXW, BYR>), grid, block, 0, h->stream, fin, fout, a); break;
-        default: hipLaunchKernelGGL((k_step<3, T, TXW, BYR>), grid, block, 0, h->stream, fin, fout, a); break;
+        if (march_fits<T>(a)) {
+            dim3 grid(8 * a.m_per_xcd), block(MW * MWPB);
+            switch (h->p.limiter) {
+            case 0: hipLaunchKernelGGL((k_march<0, T>), grid, block, 0, h->stream, fin, fout, h->args_dev); break;
+            case 1: hipLaunchKernelGGL((k_march<1, T>), grid, block, 0, h->stream, fin, fout, h->args_dev); break;
+            case 2: hipLaunchKernelGGL((k_march<2, T>), grid, block, 0, h->stream, fin, fout, h->args_dev); break;
+            default: hipLaunchKernelGGL((k_march<3, T>), grid, block, 0, h->stream, fin, fout, h->args_dev); break;
+            }
+        } else {
+            // state buffers of 2 GiB and more: the LDS-tile form
+            constexpr int TXW = TileOf<T>::TXW, BYR = TileOf<T>::BYR;
+            dim3 grid(8 * a.per_xcd), block(TXW * BYR);
+            switch (h->p.limiter) {
+            case 0: hipLaunchKernelGGL((k_step<0, T, TXW, BYR>), grid, block, 0, h->stream, fin, fout, a); break;
+            case 1: hipLaunchKernelGGL((k_step<1, T, TXW, BYR>), grid, block, 0, h->stream, fin, fout, a); break;
+            case 2: hipLaunchKernelGGL((k_step<2, T, TXW, BYR>), grid, block, 0, h->stream, fin, fout, a); break;
+            default: hipLaunchKernelGGL((k_step<3, T, TXW, BYR>), grid, block, 0, h->stream, fin, fout, a); break;
+            }
         }
         HIPCHK(hipGetLastError());
         for (int axis = 0; axis < 2; ++axis) {
@@ -166,14 +206,20 @@ int mrtfd_create(const mrtfd_params* p, void* hip_stream, mrtfd_t* out)
         return fail(MRTFD_EINVAL, "singular moment blocks for eta0 = %g", p->eta0);
     }
     if (hipMalloc(&h->flag, sizeof(int)) != hipSuccess || hipMalloc(&h->blocks_dev, sizeof(Blocks)) != hipSuccess ||
+        hipMalloc(&h->args_dev, sizeof(StepArgs)) != hipSuccess ||
         hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess) {
         (void)hipFree(h->buf[0]);
         (void)hipFree(h->buf[1]);
         delete h;
         return fail(MRTFD_EDEVICE, "device set-up failed");
     }
+    if (query_march_capacity(h) != MRTFD_OK) {
+        mrtfd_destroy(h);
+        return MRTFD_EDEVICE;
+    }
     fill_args(h);
-    if (hipMemcpyAsync(h->blocks_dev, &h->blocks, sizeof(Blocks), hipMemcpyHostToDevice, h->stream) != hipSuccess) {
+    if (hipMemcpyAsync(h->blocks_dev, &h->blocks, sizeof(Blocks), hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+        hipMemcpyAsync(h->args_dev, &h->args, sizeof(StepArgs), hipMemcpyHostToDevice, h->stream) != hipSuccess) {
         mrtfd_destroy(h);
         return fail(MRTFD_EDEVICE, "device set-up failed");
     }
@@ -195,6 +241,7 @@ int mrtfd_destroy(mrtfd_t h)
     (void)hipFree(h->buf[1]);
     (void)hipFree(h->flag);
     (void)hipFree(h->blocks_dev);
+    (void)hipFree(h->args_dev);
     if (h->staging) (void)hipFree(h->staging);
     (void)hipEventDestroy(h->ev0);
     (void)hipEventDestroy(h->ev1);

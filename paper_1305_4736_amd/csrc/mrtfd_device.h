@@ -61,6 +61,8 @@ struct StepArgs {
     int ntx, nty;               // step-kernel tiles along x and y
     int per_xcd;                // tiles per XCD slot (grid = 8 * per_xcd blocks)
     int band;                   // tile columns per band of the XCD-aware order
+    int m_nsx, m_nby, m_rows;   // row-marching form: strips, bands, rows per band
+    int m_per_xcd;              // row-marching blocks per XCD slot
     int bc[4];                  // kinds of x-lo, x-hi, y-lo, y-hi
     int correction;
     int* flag;                  // set to 1 when a node is unphysical
@@ -119,13 +121,17 @@ __host__ __device__ __forceinline__ Sums all_sums(const double* f)
     return a;
 }
 
-__host__ __device__ __forceinline__ double dot4(const double* r, const double* v)
+// (r may point into any address space: generic, or the constant space the
+// row-marching kernel reads its blocks from)
+template <class P>
+__host__ __device__ __forceinline__ double dot4(P r, const double* v)
 {
     return fma(r[0], v[0], fma(r[1], v[1], fma(r[2], v[2], r[3] * v[3])));
 }
 
 // fhat = M f from the angular sums (all 16 moments).
-__host__ __device__ __forceinline__ void moments(const Blocks& B, const Sums& a, double* m)
+template <class BT>
+__host__ __device__ __forceinline__ void moments(const BT& B, const Sums& a, double* m)
 {
     m[0] = (a.S[0] + a.S[1]) + (a.S[2] + a.S[3]);
     m[3] = dot4(B.F0[1], a.S);
@@ -178,7 +184,8 @@ __device__ __forceinline__ void equilibria(double rho, double ux, double uy, dou
 
 // v = M^-1 w for a moment vector w with w_1..w_4 = 0 (the collision residual
 // and the non-equilibrium part), using the pre-scaled inverse blocks.
-__host__ __device__ __forceinline__ void inverse_nc(const Blocks& B, const double* w, double* v)
+template <class BT>
+__host__ __device__ __forceinline__ void inverse_nc(const BT& B, const double* w, double* v)
 {
     double S[4], X[4], Y[4], D[4];
 #pragma unroll
@@ -245,7 +252,8 @@ __device__ __forceinline__ void macro_of(const Blocks& B, double inv_b, const do
 }
 
 // Density and velocity only (neighbour ring of the correction).
-__device__ __forceinline__ void velocity_of(const Blocks& B, const double* f, double& ux, double& uy)
+template <class BT>
+__device__ __forceinline__ void velocity_of(const BT& B, const double* f, double& ux, double& uy)
 {
     Sums a = all_sums(f);
     double rho = (a.S[0] + a.S[1]) + (a.S[2] + a.S[3]);
@@ -281,13 +289,22 @@ __device__ __forceinline__ R limited(R up, R dn)
 // Convective increment of one population along one axis:
 //   -nu [ (f_J - f_{J-s}) + c (L(f_J - f_{J-s}, f_{J+s} - f_J) - L(f_{J-s} - f_{J-2s}, f_J - f_{J-s})) ]
 // with c = (1 - nu) / 2, s the sign of the velocity component.
+// (conv_increment is the last step, shared by every kernel so that all of
+// them round it alike; the library is built with contraction of a * b + c
+// only within one source expression.)
+template <typename R>
+__device__ __forceinline__ R conv_increment(R l1, R l0, R d1, R nu, R c)
+{
+    return -nu * fma(c, l1 - l0, d1);
+}
+
 template <int LIM, typename R>
 __device__ __forceinline__ R conv1(R fm2, R fm1, R f0, R fp1, R nu, R c)
 {
     R d0 = fm1 - fm2, d1 = f0 - fm1, d2 = fp1 - f0;
     R l1 = limited<LIM>(d1, d2);
     R l0 = limited<LIM>(d0, d1);
-    return -nu * fma(c, l1 - l0, d1);
+    return conv_increment(l1, l0, d1, nu, c);
 }
 
 }  // namespace mrtfd

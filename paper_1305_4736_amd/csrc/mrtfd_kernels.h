@@ -88,7 +88,8 @@ __device__ void wall_fill(const StepArgs& a, T* __restrict__ f, const double* f1
 
 // Relaxed residual of the non-conserved moments, mapped back to velocity
 // space and scaled by -dt (the collision term of the update).
-__device__ __forceinline__ void collision(const StepArgs& a, const double* m, double rho, double ux, double uy,
+template <class AT, class BT>
+__device__ __forceinline__ void collision(const AT& a, const BT& B, const double* m, double rho, double ux, double uy,
                                           double P, bool corr, double dxux, double dxuy, double dyux,
                                           double dyuy, double* coll)
 {
@@ -108,14 +109,15 @@ __device__ __forceinline__ void collision(const StepArgs& a, const double* m, do
     }
 #pragma unroll
     for (int k = 4; k < NQ; ++k) w[k] *= -a.dt;
-    inverse_nc(*a.Bp, w, coll);
+    inverse_nc(B, w, coll);
 }
 
 // Periodic and outflow ghost images owned by node (x, y): up to 4 along x
 // and 4 along y (a single-node axis wraps onto all four ghosts).  Returns the
 // count; offs[] are element offsets relative to the node.  Wall nodes and
 // their ghosts are filled afterwards by k_fill (walls only).
-__device__ __forceinline__ int image_offsets(const StepArgs& a, int x, int y, int* offs)
+template <class AT>
+__device__ __forceinline__ int image_offsets(const AT& a, int x, int y, int* offs)
 {
     int n = 0;
     if (a.bc[0] == BC_PERIODIC) {
@@ -291,7 +293,7 @@ __device__ __forceinline__ void step_tile(const T* __restrict__ fin, T* __restri
     if (!active) return;
     if (!(rho > 0.0 && P > 0.0)) atomicOr(a.flag, 1);
     double coll[NQ];
-    collision(a, m, rho, ux, uy, P, corr, dxux, dxuy, dyux, dyuy, coll);
+    collision(a, *a.Bp, m, rho, ux, uy, P, corr, dxux, dxuy, dyux, dyuy, coll);
 
     // ---- limited fluxes and the update, plane by plane
     using R = T;   // convection precision (FP64, or FP32 in FP32-storage mode)

@@ -1,0 +1,335 @@
+// mrtfd_march.h -- row-marching form of the fused D2V16 MRT-FD step
+// (arXiv:1305.4736, Sec. III update eq.) for one large instance.
+//
+// A wavefront owns a strip of 64 columns and a band of rows.  Its lanes are
+// the strip's columns: the two lanes at each side are halo, the 60 inner
+// lanes produce output.  The wavefront walks the band one row at a time and
+// holds four rows of all 16 planes in registers (the rows behind, at and
+// ahead of the output row, and the next row, whose loads are in flight while
+// the current row is computed); HBM is read once per row plus four halo rows
+// per band and written once.  Neighbours along x come from the adjacent lanes
+// (DPP whole-wavefront shifts), neighbours along y from the register window.
+// The limited jump of each y face is evaluated once and carried to the next
+// row.  Every value is formed from the same operands in the same order as in
+// the LDS-tile kernel (k_step), so both give bitwise identical results.
+//
+// Periodic and outflow sides are read at their source nodes (a column is
+// remapped once per lane, a row once per row), so this kernel writes no
+// ghost images; equilibrium ghosts are constant and NEE walls are refilled
+// by a separate launch after the step.
+#pragma once
+#include <algorithm>
+
+#include "mrtfd_kernels.h"
+
+namespace {
+
+constexpr int MW = 64;           // lanes of a wavefront = columns of a strip
+constexpr int MOUT = MW - 4;     // output columns of a strip
+constexpr int MWPB = 4;          // wavefronts (independent strips) per block
+constexpr int MRMIN = 8;         // fewest rows per band when the grid is small
+
+// Whole-wavefront lane moves (DPP wave_shr:1 / wave_shl:1): lane l receives
+// the value of lane l - 1 (FROM_LEFT) or l + 1 (FROM_RIGHT); the lane at the
+// end receives 0 (bound control).  All 64 lanes must be active.
+constexpr int FROM_LEFT = 0x138;
+constexpr int FROM_RIGHT = 0x130;
+
+template <int CTRL>
+__device__ __forceinline__ double lane_move(double v)
+{
+    int lo = __double2loint(v), hi = __double2hiint(v);
+    lo = __builtin_amdgcn_mov_dpp(lo, CTRL, 0xf, 0xf, true);
+    hi = __builtin_amdgcn_mov_dpp(hi, CTRL, 0xf, 0xf, true);
+    return __hiloint2double(hi, lo);
+}
+
+template <int CTRL>
+__device__ __forceinline__ float lane_move(float v)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xf, 0xf, true));
+}
+
+// Kernel arguments and moment blocks are read through the constant address
+// space: loads from it stay scalar (s_load) even in a loop that stores.
+#define MRTFD_CONSTANT __attribute__((address_space(4)))
+using CArgs = const MRTFD_CONSTANT StepArgs;
+using CBlocks = const MRTFD_CONSTANT Blocks;
+
+__device__ __forceinline__ CBlocks& blocks_of(CArgs& a) { return *(CBlocks*)a.Bp; }
+
+// Buffer resources: loads and stores address plane i, row y of a state
+// buffer as a scalar offset (i * plane + org - 2 + y * pitch elements) plus a
+// per-lane offset (column + 2) that stays fixed for the whole walk, so no
+// per-lane address arithmetic is spent per row.  The march is only used for
+// buffers below 2 GiB, where both offsets fit 31 bits.  Lanes that must not
+// store use the per-lane offset NO_STORE: at least 2 GiB, beyond the buffer's
+// size, so the hardware range check discards the store.
+constexpr int BUF_WORD3 = 0x00020000;   // raw 32-bit data format (gfx9 family)
+constexpr unsigned NO_STORE = 0x80000000u;
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ double buf_load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, double*)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+}
+__device__ __forceinline__ float buf_load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, float*)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+__device__ __forceinline__ void buf_store(double v, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), r, (int)voff, (int)soff, 0);
+}
+__device__ __forceinline__ void buf_store(float v, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)voff, (int)soff, 0);
+}
+
+// Coordinate c in [-2, n + 1] of an axis with n nodes, mapped to the node
+// that holds its value: periodic sides wrap, outflow sides repeat the last
+// node, equilibrium and wall sides keep their stored ghosts.
+__device__ __forceinline__ int source_of(int c, int n, int lo_kind, int hi_kind)
+{
+    if (c < 0) {
+        if (lo_kind == BC_PERIODIC) return (n == 1) ? 0 : c + n;
+        if (lo_kind == BC_OUTFLOW) return 0;
+    } else if (c >= n) {
+        if (hi_kind == BC_PERIODIC) return (n == 1) ? 0 : c - n;
+        if (hi_kind == BC_OUTFLOW) return n - 1;
+    }
+    return c;
+}
+
+// One wavefront's walk through its band in direction DIR (+1: increasing y).
+// fB, fC, fD hold rows j - DIR, j, j + DIR of output row j; fE receives row
+// j + 2 DIR while row j is computed.
+template <int LIM, typename T, int DIR>
+struct Marcher {
+    using R = T;   // convection precision (FP64, or FP32 in FP32-storage mode)
+
+    CArgs* argp;                      // kernel arguments
+    __amdgpu_buffer_rsrc_t rin, rout;
+    unsigned vin;                     // per-lane load offset (bytes)
+    unsigned vout;                    // per-lane store offset, NO_STORE off the output columns
+    T fB[NQ], fC[NQ], fD[NQ], fE[NQ];
+    double uxB, uyB, uxC, uyC, uxD, uyD, uxE, uyE;
+    R carry[NQ];                      // limited jump of the y face carried from the previous row
+
+    __device__ __forceinline__ Marcher(CArgs* ap, const T* fin, T* fout, unsigned bytes, int x, bool out)
+        : argp(ap),
+          rin(__builtin_amdgcn_make_buffer_rsrc((void*)fin, (short)0, (int)bytes, BUF_WORD3)),
+          rout(__builtin_amdgcn_make_buffer_rsrc((void*)fout, (short)0, (int)bytes, BUF_WORD3)),
+          vin((unsigned)(source_of(min(x, ap->nx + 1), ap->nx, ap->bc[0], ap->bc[1]) + 2) * (unsigned)sizeof(T)),
+          vout(out ? (unsigned)(x + 2) * (unsigned)sizeof(T) : NO_STORE)
+    {
+    }
+
+    // The kernel arguments, re-read at every row: hiding the pointer from the
+    // optimiser keeps it from hoisting ~150 constant dwords out of the loop
+    // into scalar registers (they are scalar-cache hits).
+    __device__ __forceinline__ CArgs& args() const
+    {
+        CArgs* p = argp;
+        asm volatile("" : "+s"(p));
+        return *p;
+    }
+
+    __device__ __forceinline__ void load(T (&dst)[NQ], int y, CArgs& a) const
+    {
+        const int ys = source_of(y, a.ny, a.bc[2], a.bc[3]);
+        const unsigned base = (unsigned)((a.org - 2 + (long)ys * a.pitch) * (long)sizeof(T));
+        const unsigned pb = (unsigned)(a.plane * (long)sizeof(T));
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) dst[i] = buf_load(rin, vin, base + (unsigned)i * pb, (T*)nullptr);
+    }
+
+    __device__ __forceinline__ static void velocity(const T (&src)[NQ], double& vx, double& vy, CArgs& a)
+    {
+        double g[NQ];
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) g[i] = (double)src[i];
+        velocity_of(blocks_of(a), g, vx, vy);
+    }
+
+    // Limited jump of the y face carried into the first output row j0 (the
+    // value the row before j0 would have left): fE = row j0 - 2 DIR,
+    // fB = j0 - DIR, fC = j0, fD = j0 + DIR.
+    __device__ __forceinline__ void start_carry()
+    {
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) {
+            const int sy = sgy(i);
+            if (sy == DIR)
+                carry[i] = limited<LIM, R>(fB[i] - fE[i], fC[i] - fB[i]);
+            else if (sy == -DIR)
+                carry[i] = limited<LIM, R>(fC[i] - fD[i], fB[i] - fC[i]);
+        }
+    }
+
+    // New value of plane i at output row j.
+    __device__ __forceinline__ T plane_value(int i, const double* coll, CArgs& a)
+    {
+        const int g = i >> 2;
+        const R f0 = fC[i];
+        R acc = R(0);
+        const int sx = sgx(i), sy = sgy(i);
+        if (sx != 0) {
+            const R fl = lane_move<FROM_LEFT>(f0), fr = lane_move<FROM_RIGHT>(f0);
+            const R fm1 = (sx > 0) ? fl : fr, fp1 = (sx > 0) ? fr : fl;
+            const R d1 = f0 - fm1, d2 = fp1 - f0;
+            const R l1 = limited<LIM, R>(d1, d2);
+            const R l0 = (sx > 0) ? lane_move<FROM_LEFT>(l1) : lane_move<FROM_RIGHT>(l1);
+            acc += conv_increment(l1, l0, d1, (R)a.nux[g], (R)a.cx[g]);
+        }
+        if (sy != 0) {
+            R d1, l1, l0;
+            if (sy == DIR) {        // upstream row is behind: its face value is carried
+                d1 = f0 - fB[i];
+                l1 = limited<LIM, R>(d1, fD[i] - f0);
+                l0 = carry[i];
+                carry[i] = l1;
+            } else {                // upstream row is ahead: needs row j + 2 DIR
+                d1 = f0 - fD[i];
+                l1 = carry[i];
+                l0 = limited<LIM, R>(fD[i] - fE[i], d1);
+                carry[i] = l0;
+            }
+            acc += conv_increment(l1, l0, d1, (R)a.nuy[g], (R)a.cy[g]);
+        }
+        return (T)((double)f0 + (double)acc + coll[i]);
+    }
+
+    __device__ __forceinline__ void row(int j)
+    {
+        CArgs& a = args();
+        load(fE, j + 2 * DIR, a);
+
+        // moments, equilibria, correction and collision of row j
+        double m[NQ];
+        {
+            double g[NQ];
+#pragma unroll
+            for (int i = 0; i < NQ; ++i) g[i] = (double)fC[i];
+            Sums sm = all_sums(g);
+            moments(blocks_of(a), sm, m);
+        }
+        const double rho = m[0];
+        const double vx = uxC, vy = uyC;
+        const double P = (m[3] - rho * (vx * vx + vy * vy)) * a.inv_b;
+        const bool corr = a.correction != 0;
+        double dxux = 0.0, dxuy = 0.0, dyux = 0.0, dyuy = 0.0;
+        if (corr) {
+            dxux = (lane_move<FROM_RIGHT>(vx) - lane_move<FROM_LEFT>(vx)) * a.inv2dx;
+            dxuy = (lane_move<FROM_RIGHT>(vy) - lane_move<FROM_LEFT>(vy)) * a.inv2dx;
+            const double uxp = (DIR > 0) ? uxD : uxB, uxm = (DIR > 0) ? uxB : uxD;
+            const double uyp = (DIR > 0) ? uyD : uyB, uym = (DIR > 0) ? uyB : uyD;
+            dyux = (uxp - uxm) * a.inv2dy;
+            dyuy = (uyp - uym) * a.inv2dy;
+        }
+        if (vout != NO_STORE && !(rho > 0.0 && P > 0.0)) atomicOr(a.flag, 1);
+        double coll[NQ];
+        collision(a, blocks_of(a), m, rho, vx, vy, P, corr, dxux, dxuy, dyux, dyuy, coll);
+
+        const unsigned base = (unsigned)((a.org - 2 + (long)j * a.pitch) * (long)sizeof(T));
+        const unsigned pb = (unsigned)(a.plane * (long)sizeof(T));
+        // planes that do not need row j + 2 DIR first, so its loads have time
+#pragma unroll
+        for (int pass = 0; pass < 2; ++pass) {
+#pragma unroll
+            for (int i = 0; i < NQ; ++i) {
+                if ((pass == 1) != (sgy(i) == -DIR)) continue;
+                buf_store(plane_value(i, coll, a), rout, vout, base + (unsigned)i * pb);
+            }
+        }
+        velocity(fE, uxE, uyE, a);
+    }
+
+    // Output rows [yb, ye), walked from yb up (DIR > 0) or from ye - 1 down.
+    __device__ __forceinline__ void walk(int yb, int ye)
+    {
+        if (ye <= yb) return;
+        int j = (DIR > 0) ? yb : ye - 1;
+        {
+            CArgs& a = args();
+            load(fE, j - 2 * DIR, a);
+            load(fB, j - DIR, a);
+            load(fC, j, a);
+            load(fD, j + DIR, a);
+            velocity(fB, uxB, uyB, a);
+            velocity(fC, uxC, uyC, a);
+            velocity(fD, uxD, uyD, a);
+        }
+        start_carry();
+        for (int left = ye - yb;;) {
+            row(j);
+            if (--left == 0) break;
+            j += DIR;
+#pragma unroll
+            for (int i = 0; i < NQ; ++i) {
+                fB[i] = fC[i];
+                fC[i] = fD[i];
+                fD[i] = fE[i];
+            }
+            uxB = uxC; uyB = uyC;
+            uxC = uxD; uyC = uyD;
+            uxD = uxE; uyD = uyE;
+        }
+    }
+};
+
+// The step of one instance (arguments in device memory): wavefront w of
+// block b takes work item ((b mod 8) * per_xcd + b / 8) * MWPB + w (blocks go
+// round-robin to the 8 XCDs, so each XCD sweeps a contiguous range of
+// items); items are numbered band after band, strip by strip within a band.
+// Adjacent bands march in opposite directions, so the halo rows two bands
+// share are read by both at about the same time.
+template <int LIM, typename T>
+__global__ void __launch_bounds__(MW * MWPB) k_march(const T* __restrict__ fin, T* __restrict__ fout,
+                                                    const StepArgs* __restrict__ ap)
+{
+    CArgs& a = *(CArgs*)ap;
+    // the wavefront index is uniform across the wavefront: say so, so that
+    // band, strip and row offsets live in scalar registers
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / MW)), lane = threadIdx.x % MW;
+    const int bid = blockIdx.x;
+    const int item = ((bid & 7) * a.m_per_xcd + (bid >> 3)) * MWPB + w;
+    if (item >= a.m_nsx * a.m_nby) return;     // whole wavefront
+    const int band = item / a.m_nsx, strip = item - band * a.m_nsx;
+    const int x = a.x0 + strip * MOUT - 2 + lane;
+    const bool out = lane >= 2 && lane < MW - 2 && x < a.x1;
+    const int yb = a.y0 + band * a.m_rows, ye = min(yb + a.m_rows, a.y1);
+    const unsigned bytes = (unsigned)(NQ * a.plane * (long)sizeof(T));
+    if (band & 1) {
+        Marcher<LIM, T, -1> mr(&a, fin, fout, bytes, x, out);
+        mr.walk(yb, ye);
+    } else {
+        Marcher<LIM, T, 1> mr(&a, fin, fout, bytes, x, out);
+        mr.walk(yb, ye);
+    }
+}
+
+// The march addresses a state buffer with 31-bit byte offsets.
+template <typename T>
+inline bool march_fits(const StepArgs& a)
+{
+    return (double)NQ * (double)a.plane * (double)sizeof(T) < 2147483648.0;
+}
+
+// Strips, bands and rows per band: as many bands as keep every wavefront of
+// the launch resident at once (capacity_waves), but at least MRMIN rows per
+// band unless the grid has fewer rows.
+inline void set_march(StepArgs& a, long capacity_waves)
+{
+    const int ex = a.x1 - a.x0, ey = a.y1 - a.y0;
+    a.m_nsx = (ex + MOUT - 1) / MOUT;
+    long nby = capacity_waves / (a.m_nsx > 0 ? a.m_nsx : 1);
+    nby = std::max(1L, std::min(nby, (long)((ey + MRMIN - 1) / MRMIN)));
+    a.m_rows = (int)((ey + nby - 1) / nby);
+    if (a.m_rows < 1) a.m_rows = 1;
+    a.m_nby = (ey + a.m_rows - 1) / a.m_rows;
+    const int nblk = (a.m_nsx * a.m_nby + MWPB - 1) / MWPB;
+    a.m_per_xcd = (nblk + 7) / 8;
+}
+
+}  // namespace
