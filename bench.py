@@ -142,7 +142,8 @@ def cpu_baseline(log, nsteps=2):
 
 def run_batched(steps, warmup, log, n=512):
     """512 independent Riemann instances (log-uniform Nx in [128, 4096], Ny in
-    [1, 256], seeded states) in one batch, FP32 storage, autotuned tiles."""
+    [1, 256], seeded states) in one batch, FP32 storage, autotuned shape
+    classes."""
     from paper_1305_4736_amd import mrtfd, workloads as W
 
     cases, redraws = W.riemann_batch(n=n, precision="fp32")
@@ -151,9 +152,11 @@ def run_batched(steps, warmup, log, n=512):
     for c in cases:
         b.add(c["params"], c["rho"], c["ux"], c["uy"], c["T"])
     costs = b.autotune()
+    names = list(mrtfd.SHAPE_CLASSES)
     shapes = {}
     for k in range(n):
-        sh = "x".join(map(str, b.shape(k)))
+        tx, ty = b.shape(k)
+        sh = "strips" if tx == 60 else f"tile{tx}x{ty}"
         shapes[sh] = shapes.get(sh, 0) + 1
     b.step(warmup)
     b.sync()
@@ -169,8 +172,8 @@ def run_batched(steps, warmup, log, n=512):
     return {"workload": f"riemann_batch_{n}", "instances": n, "nodes": nodes, "precision": "fp32",
             "limiter": "mc", "steps": steps, "ms_per_step": ms / steps, "value": value,
             "unit": "node-updates/s", "screen_redraws": redraws, "nonfinite_instances": nonfinite,
-            "autotune_us_per_tile": {"32x8": costs[0], "64x4": costs[1], "128x2": costs[2], "256x1": costs[3]},
-            "tile_shapes": shapes}
+            "autotune_us_per_unit": dict(zip(names, map(float, costs))),
+            "shape_classes": shapes}
 
 
 def run_served(rate, seconds, log, drain, label, steps_per_tick=50, capacity=4096, cap_bytes=None):

@@ -206,15 +206,26 @@ int mrtfd_batch_set_f(mrtfd_batch_t b, int slot, const double* f, int on_device)
 int mrtfd_batch_status(mrtfd_batch_t b, int* flags);
 int mrtfd_batch_sync(mrtfd_batch_t b);
 
-/* Tile shape chosen for a slot (nodes per block along x and y). */
+/* Work decomposition of a slot: its shape class (see below) as the output
+ * nodes per work item along x and y (txw x byr); for the row-marching
+ * strips, 60 columns by the rows of one band. */
 int mrtfd_batch_shape(mrtfd_batch_t b, int slot, int* txw, int* byr);
 
-/* Autotuner: measure the device time per tile of each tile shape (32 x 8,
- * 64 x 4, 128 x 2, and 256 x 1 for one-row instances) on calibration
- * instances, write them to cost_per_tile_us[4] (may be NULL), and give every
- * slot the shape with the smallest tiles x cost.  Slot states are
+/* Shape classes of a slot: 0..3 are LDS tiles of 256 nodes (32 x 8, 64 x 4,
+ * 128 x 2, and 256 x 1 for one-row instances whose y sides are periodic or
+ * outflow); 4 is the row-marching form (one wavefront per strip of 60
+ * columns and band of up to 32 rows; instances whose state buffer is below
+ * 2 GiB).  All classes give bitwise identical results.  Force a slot into
+ * class `shape` (for tuning and comparison); the slot's state is kept.
+ * MRTFD_EINVAL for an unknown class or one that does not fit the slot. */
+int mrtfd_batch_set_shape(mrtfd_batch_t b, int slot, int shape);
+
+/* Autotuner: measure the device time per work unit of each shape class (a
+ * tile; a strip row including its bands' halo rows) on calibration
+ * instances, write them to cost_per_unit_us[5] (may be NULL), and give
+ * every slot the class with the smallest units x cost.  Slot states are
  * untouched; later additions use the measured costs. */
-int mrtfd_batch_autotune(mrtfd_batch_t b, double* cost_per_tile_us);
+int mrtfd_batch_autotune(mrtfd_batch_t b, double* cost_per_unit_us);
 
 #ifdef __cplusplus
 }

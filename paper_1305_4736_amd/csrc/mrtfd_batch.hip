@@ -10,10 +10,13 @@
 // and the work lists (stream-ordered copies), never the state of the others:
 // a slot's result does not depend on which other slots share its launches.
 //
-// Tile shapes (all 256 threads): 32 x 8, 64 x 4, 128 x 2, and 256 x 1 rows
-// for one-row instances.  Each slot gets the shape with the smallest
-// estimated cost (tiles x cost per tile); mrtfd_batch_autotune measures the
-// cost per tile of every shape on calibration grids and reassigns.
+// Shape classes: the row-marching strips of mrtfd_march.h (60 output
+// columns x bands of up to 32 rows per wavefront), and LDS tiles of 256
+// threads: 32 x 8, 64 x 4, 128 x 2, and 256 x 1 rows for one-row instances.
+// Each slot gets the class with the smallest estimated cost (work units x
+// cost per unit; a unit is a tile, or one row of a strip including the halo
+// rows of its bands); mrtfd_batch_autotune measures the cost per unit of
+// every class on calibration grids and reassigns.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -22,31 +25,52 @@
 #include <vector>
 
 #include "mrtfd_host.h"
+#include "mrtfd_march.h"
 
 using namespace mrtfd;
 
 namespace {
 
-constexpr int NSHAPE = 4;
+constexpr int NSHAPE = 5;
+constexpr int MARCH = 4;   // index of the row-marching class
 struct ShapeDef {
     int txw, byr;
     bool flat;
 };
-constexpr ShapeDef SHAPES[NSHAPE] = {{32, 8, false}, {64, 4, false}, {128, 2, false}, {256, 1, true}};
+constexpr ShapeDef SHAPES[NSHAPE] = {{32, 8, false}, {64, 4, false}, {128, 2, false}, {256, 1, true}, {MOUT, MBROWS, false}};
+// Cost per work unit before autotuning (microseconds, measured on the
+// 4096 x 1024 shock-interface grid in FP32 storage; only the ratios matter).
+constexpr double DEFAULT_COST[NSHAPE] = {0.028, 0.028, 0.029, 0.045, 0.0019};
 
 bool shape_fits(const mrtfd_params& p, int s)
 {
+    if (s == MARCH) {
+        const Layout L = layout_of(p);
+        return (double)L.buf_bytes < 2147483648.0;
+    }
     if (!SHAPES[s].flat) return true;
     // one row whose y ghosts copy the row
     return p.ny == 1 && (p.bc[2].kind == BC_PERIODIC || p.bc[2].kind == BC_OUTFLOW) &&
            (p.bc[3].kind == BC_PERIODIC || p.bc[3].kind == BC_OUTFLOW);
 }
 
+// Work units of an instance in class s (tiles; for strips, strip rows
+// including the four halo rows each band loads).
 long tiles_of(const mrtfd_params& p, int s)
 {
     const int ex = p.nx - (p.bc[0].kind == BC_WALL) - (p.bc[1].kind == BC_WALL);
     const int ey = p.ny - (p.bc[2].kind == BC_WALL) - (p.bc[3].kind == BC_WALL);
+    if (s == MARCH) {
+        const long nby = (ey + MBROWS - 1) / MBROWS;
+        return (long)((ex + MOUT - 1) / MOUT) * (ey + 4 * nby);
+    }
     return (long)((ex + SHAPES[s].txw - 1) / SHAPES[s].txw) * ((ey + SHAPES[s].byr - 1) / SHAPES[s].byr);
+}
+
+// Work items of one launch for a slot in class s.
+long items_of(const StepArgs& a, int s)
+{
+    return (s == MARCH) ? (long)a.m_nsx * a.m_nby : (long)a.ntx * a.nty;
 }
 
 }  // namespace
@@ -71,6 +95,7 @@ struct mrtfd_batch_s {
     size_t staging_bytes;
     hipEvent_t ev0, ev1;
     int max_blocks;
+    int march_blocks;                   // resident blocks of the strip kernel on the device
 };
 
 namespace {
@@ -103,8 +128,10 @@ int pick_shape(const mrtfd_batch_s* B, const mrtfd_params& p)
 
 void set_args(mrtfd_batch_s* B, int k)
 {
-    const ShapeDef& sd = SHAPES[B->shape[k]];
+    const int s = B->shape[k];
+    const ShapeDef& sd = SHAPES[s == MARCH ? 0 : s];
     B->slot[k].a = make_args(B->prm[k], B->lay[k], B->blk[k], B->d_blocks + k, B->d_flags + k, sd.txw, sd.byr, 1 << 20);
+    set_march_rows(B->slot[k].a, MBROWS);
 }
 
 int upload_slot(mrtfd_batch_s* B, int k)
@@ -126,7 +153,7 @@ int rebuild_lists(mrtfd_batch_s* B)
             if (!B->used[k] || B->shape[k] != s || B->L >= B->slot[k].stop) continue;
             pre[n] = acc;
             lst[n] = k;
-            acc += B->slot[k].a.ntx * B->slot[k].a.nty;
+            acc += (int)items_of(B->slot[k].a, s);
             ++n;
         }
         pre[n] = acc;
@@ -148,10 +175,19 @@ int rebuild_lists(mrtfd_batch_s* B)
 template <int LIM, typename T>
 int launch_shape(mrtfd_batch_s* B, int s, long items)
 {
-    const int grid = (int)std::min<long>(items, B->max_blocks);
     const int* pre = prefix_dev(B, s);
     const int* lst = list_dev(B, s);
     const int n = B->nlist[s];
+    if (s == MARCH) {
+        // persistent wavefronts; the XCD-aware numbering needs a multiple of 8 blocks
+        long blocks = std::min<long>((items + MWPB - 1) / MWPB, B->march_blocks);
+        blocks = (blocks + 7) / 8 * 8;
+        hipLaunchKernelGGL((k_march_batch<LIM, T>), dim3((int)blocks), dim3(MW * MWPB), 0, B->stream, B->d_slot, pre,
+                           lst, n, B->L);
+        HIPCHK(hipGetLastError());
+        return MRTFD_OK;
+    }
+    const int grid = (int)std::min<long>(items, B->max_blocks);
     switch (s) {
     case 0: hipLaunchKernelGGL((k_step_batch<LIM, T, 32, 8, false>), dim3(grid), dim3(256), 0, B->stream, B->d_slot, pre, lst, n, B->L); break;
     case 1: hipLaunchKernelGGL((k_step_batch<LIM, T, 64, 4, false>), dim3(grid), dim3(256), 0, B->stream, B->d_slot, pre, lst, n, B->L); break;
@@ -173,7 +209,7 @@ int launch_step_batch_t(mrtfd_batch_s* B)
         if (!B->nlist[s]) continue;
         long items = 0;
         for (int k = 0; k < B->capacity; ++k)
-            if (B->used[k] && B->shape[k] == s && B->L < B->slot[k].stop) items += (long)B->slot[k].a.ntx * B->slot[k].a.nty;
+            if (B->used[k] && B->shape[k] == s && B->L < B->slot[k].stop) items += items_of(B->slot[k].a, s);
         int rc = 0;
         switch (B->limiter) {
         case 0: rc = launch_shape<0, T>(B, s, items); break;
@@ -224,6 +260,50 @@ int current_buffer(const mrtfd_batch_s* B, int k)
 }
 
 template <typename T>
+const void* march_batch_kernel(int limiter)
+{
+    switch (limiter) {
+    case 0: return (const void*)k_march_batch<0, T>;
+    case 1: return (const void*)k_march_batch<1, T>;
+    case 2: return (const void*)k_march_batch<2, T>;
+    default: return (const void*)k_march_batch<3, T>;
+    }
+}
+
+// Rewrite every ghost layer of a slot's current buffer from its interior.
+template <typename T>
+int refill_current_t(mrtfd_batch_s* B, int k)
+{
+    const mrtfd_params& p = B->prm[k];
+    T* f = (T*)B->slot[k].buf[current_buffer(B, k)];
+    for (int axis = 0; axis < 2; ++axis) {
+        const int n = 2 * ((axis == 0) ? p.ny : p.nx);
+        hipLaunchKernelGGL((k_fill<T>), dim3((n + 127) / 128), dim3(128), 0, B->stream, f, B->slot[k].a, axis, 0);
+        HIPCHK(hipGetLastError());
+    }
+    return MRTFD_OK;
+}
+
+// Move slot k to shape class s.  The strip kernel reads periodic and
+// outflow sides at their source nodes and leaves those ghosts stale, while
+// the tile kernels read the ghosts: leaving the strip class refills them.
+int assign_shape(mrtfd_batch_s* B, int k, int s)
+{
+    const int old = B->shape[k];
+    if (old == s) return MRTFD_OK;
+    B->shape[k] = s;
+    set_args(B, k);
+    int rc = upload_slot(B, k);
+    if (rc) return rc;
+    if (old == MARCH) {
+        rc = (B->precision == MRTFD_FP32_STORAGE) ? refill_current_t<float>(B, k) : refill_current_t<double>(B, k);
+        if (rc) return rc;
+    }
+    B->dirty = true;
+    return MRTFD_OK;
+}
+
+template <typename T>
 int init_slot_t(mrtfd_batch_s* B, int k, const double* const* src, const double* fsrc)
 {
     const StepArgs& a = B->slot[k].a;
@@ -271,7 +351,7 @@ int mrtfd_batch_create(int capacity, int precision, int limiter, void* hip_strea
     B->blk.resize(capacity);
     B->used.assign(capacity, 0);
     B->shape.assign(capacity, 0);
-    for (int s = 0; s < NSHAPE; ++s) B->cost[s] = 1.0;   // until measured: fewest tiles wins
+    for (int s = 0; s < NSHAPE; ++s) B->cost[s] = DEFAULT_COST[s];
     const size_t lists = (size_t)(NSHAPE * (capacity + 1) + NSHAPE * capacity + capacity) * sizeof(int);
     if (hipMalloc(&B->d_slot, capacity * sizeof(BatchSlot)) != hipSuccess ||
         hipMalloc(&B->d_blocks, capacity * sizeof(Blocks)) != hipSuccess ||
@@ -289,6 +369,10 @@ int mrtfd_batch_create(int capacity, int precision, int limiter, void* hip_strea
     int dev = 0, ncu = 256;
     if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     B->max_blocks = 4 * ncu;   // persistent grid: a few resident blocks per CU
+    int nb = 0;
+    const void* km = (precision == MRTFD_FP32_STORAGE) ? march_batch_kernel<float>(limiter) : march_batch_kernel<double>(limiter);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, km, MW * MWPB, 0) != hipSuccess) (void)hipGetLastError();
+    B->march_blocks = std::max(nb, 1) * ncu;
     B->dirty = true;
     *out = B;
     return MRTFD_OK;
@@ -552,14 +636,25 @@ int mrtfd_batch_shape(mrtfd_batch_t B, int k, int* txw, int* byr)
 {
     int rc = check_slot(B, k);
     if (rc) return rc;
-    if (txw) *txw = SHAPES[B->shape[k]].txw;
-    if (byr) *byr = SHAPES[B->shape[k]].byr;
+    const bool m = B->shape[k] == MARCH;
+    if (txw) *txw = m ? MOUT : SHAPES[B->shape[k]].txw;
+    if (byr) *byr = m ? B->slot[k].a.m_rows : SHAPES[B->shape[k]].byr;
     return MRTFD_OK;
 }
 
-// Measure the cost per tile of every shape on calibration instances (a 2-D
-// grid for the three 2-D shapes, a one-row grid for the row shape), then
-// give every occupied slot the cheapest shape.  Slot states are untouched.
+int mrtfd_batch_set_shape(mrtfd_batch_t B, int k, int shape)
+{
+    int rc = check_slot(B, k);
+    if (rc) return rc;
+    if (shape < 0 || shape >= NSHAPE) return fail(MRTFD_EINVAL, "unknown shape class %d", shape);
+    if (!shape_fits(B->prm[k], shape)) return fail(MRTFD_EINVAL, "shape class %d does not fit slot %d", shape, k);
+    return assign_shape(B, k, shape);
+}
+
+// Measure the cost per work unit of every shape class on calibration
+// instances (a 2-D grid for the strips and the three 2-D tiles, a one-row
+// grid for the row tile), then give every occupied slot the cheapest class.
+// Slot states are untouched.
 int mrtfd_batch_autotune(mrtfd_batch_t B, double* cost_per_tile_us)
 {
     if (!B) return fail(MRTFD_EINVAL, "NULL batch");
@@ -592,16 +687,12 @@ int mrtfd_batch_autotune(mrtfd_batch_t B, double* cost_per_tile_us)
         const long tiles = tiles_of(p, s);
         mrtfd_batch_destroy(C);
         if (rc) return rc;
-        B->cost[s] = 1e3 * ms / 20.0 / (double)tiles;   // microseconds per tile
+        B->cost[s] = 1e3 * ms / 20.0 / (double)tiles;   // microseconds per work unit
         if (cost_per_tile_us) cost_per_tile_us[s] = B->cost[s];
     }
     for (int k = 0; k < B->capacity; ++k) {
         if (!B->used[k]) continue;
-        const int s = pick_shape(B, B->prm[k]);
-        if (s == B->shape[k]) continue;
-        B->shape[k] = s;
-        set_args(B, k);
-        int rc = upload_slot(B, k);
+        int rc = assign_shape(B, k, pick_shape(B, B->prm[k]));
         if (rc) return rc;
     }
     B->dirty = true;

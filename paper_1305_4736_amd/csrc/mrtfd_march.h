@@ -28,6 +28,9 @@ constexpr int MW = 64;           // lanes of a wavefront = columns of a strip
 constexpr int MOUT = MW - 4;     // output columns of a strip
 constexpr int MWPB = 4;          // wavefronts (independent strips) per block
 constexpr int MRMIN = 8;         // fewest rows per band when the grid is small
+#ifndef MARCH_PF
+#define MARCH_PF 1               // rows between issuing a row's loads and first using it
+#endif
 
 // Whole-wavefront lane moves (DPP wave_shr:1 / wave_shl:1): lane l receives
 // the value of lane l - 1 (FROM_LEFT) or l + 1 (FROM_RIGHT); the lane at the
@@ -102,8 +105,10 @@ __device__ __forceinline__ int source_of(int c, int n, int lo_kind, int hi_kind)
 }
 
 // One wavefront's walk through its band in direction DIR (+1: increasing y).
-// fB, fC, fD hold rows j - DIR, j, j + DIR of output row j; fE receives row
-// j + 2 DIR while row j is computed.
+// fB, fC, fD hold rows j - DIR, j, j + DIR of output row j and fE row
+// j + 2 DIR.  With MARCH_PF = 1 the loads of row j + 2 DIR are issued at the
+// start of row j; with MARCH_PF = 2 they were issued one row earlier and fF
+// receives row j + 3 DIR while row j is computed.
 template <int LIM, typename T, int DIR>
 struct Marcher {
     using R = T;   // convection precision (FP64, or FP32 in FP32-storage mode)
@@ -112,7 +117,7 @@ struct Marcher {
     __amdgpu_buffer_rsrc_t rin, rout;
     unsigned vin;                     // per-lane load offset (bytes)
     unsigned vout;                    // per-lane store offset, NO_STORE off the output columns
-    T fB[NQ], fC[NQ], fD[NQ], fE[NQ];
+    T fB[NQ], fC[NQ], fD[NQ], fE[NQ], fF[NQ];
     double uxB, uyB, uxC, uyC, uxD, uyD, uxE, uyE;
     R carry[NQ];                      // limited jump of the y face carried from the previous row
 
@@ -137,7 +142,9 @@ struct Marcher {
 
     __device__ __forceinline__ void load(T (&dst)[NQ], int y, CArgs& a) const
     {
-        const int ys = source_of(y, a.ny, a.bc[2], a.bc[3]);
+        // rows beyond the ghost layers are only ever prefetched past a band's
+        // end and never used: read the last ghost row instead
+        const int ys = source_of(max(-2, min(y, a.ny + 1)), a.ny, a.bc[2], a.bc[3]);
         const unsigned base = (unsigned)((a.org - 2 + (long)ys * a.pitch) * (long)sizeof(T));
         const unsigned pb = (unsigned)(a.plane * (long)sizeof(T));
 #pragma unroll
@@ -203,7 +210,10 @@ struct Marcher {
     __device__ __forceinline__ void row(int j)
     {
         CArgs& a = args();
-        load(fE, j + 2 * DIR, a);
+        if (MARCH_PF == 1)
+            load(fE, j + 2 * DIR, a);
+        else
+            load(fF, j + 3 * DIR, a);
 
         // moments, equilibria, correction and collision of row j
         double m[NQ];
@@ -261,6 +271,7 @@ struct Marcher {
             velocity(fD, uxD, uyD, a);
         }
         start_carry();
+        if (MARCH_PF == 2) load(fE, j + 2 * DIR, args());
         for (int left = ye - yb;;) {
             row(j);
             if (--left == 0) break;
@@ -270,6 +281,7 @@ struct Marcher {
                 fB[i] = fC[i];
                 fC[i] = fD[i];
                 fD[i] = fE[i];
+                if (MARCH_PF == 2) fE[i] = fF[i];
             }
             uxB = uxC; uyB = uyC;
             uxC = uxD; uyC = uyD;
@@ -330,6 +342,70 @@ inline void set_march(StepArgs& a, long capacity_waves)
     a.m_nby = (ey + a.m_rows - 1) / a.m_rows;
     const int nblk = (a.m_nsx * a.m_nby + MWPB - 1) / MWPB;
     a.m_per_xcd = (nblk + 7) / 8;
+}
+
+}  // namespace
+
+namespace {
+
+constexpr int MBROWS = 32;       // rows per band of a batched instance
+
+// Band layout of a batched instance: bands of at most MBROWS rows.
+inline void set_march_rows(StepArgs& a, int rows)
+{
+    const int ex = a.x1 - a.x0, ey = a.y1 - a.y0;
+    a.m_nsx = (ex + MOUT - 1) / MOUT;
+    a.m_rows = std::max(1, std::min(rows, ey));
+    a.m_nby = (ey + a.m_rows - 1) / a.m_rows;
+    a.m_per_xcd = 0;
+}
+
+// Batched form: persistent wavefronts stride over the (band, strip) items
+// of the listed slots, numbered slot after slot (prefix[k] = first item of
+// list[k]); wavefront g of the launch takes items g, g + G, ... where the
+// wavefronts of each XCD are numbered contiguously (the grid is a multiple
+// of 8 blocks).  A launch counter L decides each slot's current buffer and
+// whether it still steps, as in the tile form.
+template <int LIM, typename T>
+__global__ void __launch_bounds__(MW * MWPB) k_march_batch(const BatchSlot* __restrict__ slots,
+                                                          const int* __restrict__ prefix,
+                                                          const int* __restrict__ list, int nlist, long L)
+{
+    const MRTFD_CONSTANT BatchSlot* cs = (const MRTFD_CONSTANT BatchSlot*)slots;
+    const MRTFD_CONSTANT int* cpre = (const MRTFD_CONSTANT int*)prefix;
+    const MRTFD_CONSTANT int* clist = (const MRTFD_CONSTANT int*)list;
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / MW)), lane = threadIdx.x % MW;
+    const int nb = gridDim.x, bid = blockIdx.x;
+    const int g = ((bid & 7) * (nb >> 3) + (bid >> 3)) * MWPB + w;
+    const int G = nb * MWPB;
+    const int nitems = cpre[nlist];
+    for (int item = g; item < nitems; item += G) {
+        int lo = 0, hi = nlist;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (cpre[mid] <= item) lo = mid;
+            else hi = mid;
+        }
+        const MRTFD_CONSTANT BatchSlot& sl = cs[clist[lo]];
+        if (L >= sl.stop) continue;
+        CArgs& a = sl.a;
+        const int par = (int)((L - sl.start) & 1);
+        const T* fin = (const T*)sl.buf[par];
+        T* fout = (T*)sl.buf[par ^ 1];
+        const int r = item - cpre[lo];
+        const int band = r / a.m_nsx, strip = r - band * a.m_nsx;
+        const int x = a.x0 + strip * MOUT - 2 + lane;
+        const bool out = lane >= 2 && lane < MW - 2 && x < a.x1;
+        const int yb = a.y0 + band * a.m_rows, ye = min(yb + a.m_rows, a.y1);
+        const unsigned bytes = (unsigned)(NQ * a.plane * (long)sizeof(T));
+        if (band & 1) {
+            Marcher<LIM, T, -1> mr(&a, fin, fout, bytes, x, out);
+            mr.walk(yb, ye);
+        } else {
+            Marcher<LIM, T, 1> mr(&a, fin, fout, bytes, x, out);
+            mr.walk(yb, ye);
+        }
+    }
 }
 
 }  // namespace

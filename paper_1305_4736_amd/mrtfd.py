@@ -271,6 +271,10 @@ _lib.mrtfd_batch_status.argtypes = [_B, ctypes.POINTER(ctypes.c_int)]
 _lib.mrtfd_batch_sync.argtypes = [_B]
 _lib.mrtfd_batch_shape.argtypes = [_B, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
 _lib.mrtfd_batch_autotune.argtypes = [_B, _dp]
+_lib.mrtfd_batch_set_shape.argtypes = [_B, ctypes.c_int, ctypes.c_int]
+
+# shape classes of a batch slot (see Batch.set_shape)
+SHAPE_CLASSES = {"tile32x8": 0, "tile64x4": 1, "tile128x2": 2, "row256": 3, "strips": 4}
 
 
 class Batch:
@@ -388,9 +392,18 @@ class Batch:
         _check(_lib.mrtfd_batch_shape(self._b, int(slot), ctypes.byref(tx), ctypes.byref(ty)))
         return tx.value, ty.value
 
+    def set_shape(self, slot: int, shape):
+        """Force a slot into a shape class (a name of SHAPE_CLASSES or its
+        index); the state is kept and every class gives the same result."""
+        k = SHAPE_CLASSES[shape] if isinstance(shape, str) else int(shape)
+        _check(_lib.mrtfd_batch_set_shape(self._b, int(slot), k))
+        return self
+
     def autotune(self):
-        """Measured device time per tile (microseconds) of the tile shapes
-        32x8, 64x4, 128x2, 256x1; every slot then gets its cheapest shape."""
-        c = np.zeros(4)
+        """Measured device time per work unit (microseconds) of the shape
+        classes tile32x8, tile64x4, tile128x2, row256, strips (a unit is a
+        tile, or a strip row with its bands' halo rows); every slot then gets
+        its cheapest class."""
+        c = np.zeros(len(SHAPE_CLASSES))
         _check(_lib.mrtfd_batch_autotune(self._b, c.ctypes.data_as(_dp)))
         return c

@@ -4,6 +4,9 @@ rates and boundaries advance in shared persistent launches.
 * each slot matches the FP64 oracle (1e-11 FP64 storage, 2e-5 FP32);
 * each slot's result is the same alone and in the mix (bitwise), and the
   same as the single-instance entry point;
+* every shape class (LDS tiles and row-marching strips) gives the same
+  bits as the single-instance entry point, also when a slot changes class
+  mid-run;
 * per-slot step budgets, slots added and removed mid-run, the autotuner's
   shape reassignment and a non-finite slot leave the other slots' results
   unchanged.
@@ -57,8 +60,9 @@ def test_batch_matches_oracle(lib, orc, precision):
     n = 40
     with lib.Batch(len(cases) + 3, precision=precision) as b:
         slots = add_all(b, cases)
-        shapes = {b.shape(s) for s in slots}
-        assert (256, 1) in shapes          # one-row instances get the row tile
+        for s in slots:
+            tx, ty = b.shape(s)
+            assert (tx, ty) in {(32, 8), (64, 4), (128, 2), (256, 1)} or (tx == 60 and 1 <= ty <= 32)
         b.step(n)
         b.status()
         for c, s in zip(cases, slots):
@@ -86,6 +90,53 @@ def test_alone_equals_mix(lib):
             single.init(c["rho"], c["ux"], c["uy"], c["T"])
             single.step(n)
             assert np.array_equal(single.get_f(), fm), c["name"]
+
+
+def single_f(lib, c, n):
+    with lib.Solver(c["params"]) as single:
+        single.init(c["rho"], c["ux"], c["uy"], c["T"])
+        single.step(n)
+        return single.get_f()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_every_shape_class_matches_single(lib, precision):
+    cases = [dict(c, params=dict(c["params"], precision=precision)) for c in mixed_cases()]
+    n = 17
+    ref = [single_f(lib, c, n) for c in cases]
+    for name, cls in lib.SHAPE_CLASSES.items():
+        with lib.Batch(len(cases), precision=precision) as b:
+            slots = add_all(b, cases)
+            forced = []
+            for k, s in enumerate(slots):
+                try:
+                    b.set_shape(s, cls)
+                    forced.append(k)
+                except lib.MRTFDError:
+                    assert name == "row256" and cases[k]["params"]["ny"] > 1
+            assert forced, name
+            b.step(n)
+            for k in forced:
+                assert np.array_equal(b.get_f(slots[k]), ref[k]), (name, cases[k]["name"])
+
+
+def test_class_change_mid_run(lib):
+    # strips (which leave periodic / outflow ghosts stale) -> tile -> strips
+    cases = mixed_cases()
+    ref = [single_f(lib, c, 24) for c in cases]
+    with lib.Batch(len(cases)) as b:
+        slots = add_all(b, cases)
+        for s in slots:
+            b.set_shape(s, "strips")
+        b.step(8)
+        for s in slots:
+            b.set_shape(s, "tile64x4")
+        b.step(8)
+        for s in slots:
+            b.set_shape(s, "strips")
+        b.step(8)
+        for k, s in enumerate(slots):
+            assert np.array_equal(b.get_f(s), ref[k]), cases[k]["name"]
 
 
 def test_budgets_and_membership_changes(lib):
