@@ -54,7 +54,7 @@ void fill_args(mrtfd_s* h)
     const bool f32 = h->p.precision == MRTFD_FP32_STORAGE;
     h->args = make_args(h->p, h->L, h->blocks, h->blocks_dev, h->flag, f32 ? STEP_TXW32 : STEP_TXW64,
                         f32 ? STEP_BYR32 : STEP_BYR64, STEP_BAND);
-    set_march(h->args, h->march_capacity);
+    set_march(h->args, h->march_capacity, f32 ? MARCH_FRAC32 : MARCH_FRAC64);
 }
 
 template <typename T>

@@ -31,6 +31,25 @@ constexpr int MRMIN = 8;         // fewest rows per band when the grid is small
 #ifndef MARCH_PF
 #define MARCH_PF 1               // rows between issuing a row's loads and first using it
 #endif
+#ifndef MARCH_LOAD_AUX
+#define MARCH_LOAD_AUX 0         // cache policy bits of the state loads
+#endif
+#ifndef MARCH_STORE_AUX
+#define MARCH_STORE_AUX 0        // cache policy bits of the state stores
+#endif
+#ifndef MARCH_ALTERNATE
+#define MARCH_ALTERNATE 1        // adjacent bands march in opposite directions
+#endif
+// Bands are sized so that the launch has this fraction of the wavefronts
+// the device holds at once.  FP64 does best with about one wavefront per
+// SIMD (longer bands: fewer halo rows and fewer concurrent streams); FP32,
+// whose step is bound by its FP64 collision arithmetic, with two.
+#ifndef MARCH_FRAC64
+#define MARCH_FRAC64 0.5
+#endif
+#ifndef MARCH_FRAC32
+#define MARCH_FRAC32 1.0
+#endif
 
 // Whole-wavefront lane moves (DPP wave_shr:1 / wave_shl:1): lane l receives
 // the value of lane l - 1 (FROM_LEFT) or l + 1 (FROM_RIGHT); the lane at the
@@ -74,19 +93,19 @@ typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ double buf_load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, double*)
 {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, MARCH_LOAD_AUX));
 }
 __device__ __forceinline__ float buf_load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, float*)
 {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, MARCH_LOAD_AUX));
 }
 __device__ __forceinline__ void buf_store(double v, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff)
 {
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), r, (int)voff, (int)soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), r, (int)voff, (int)soff, MARCH_STORE_AUX);
 }
 __device__ __forceinline__ void buf_store(float v, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff)
 {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)voff, (int)soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)voff, (int)soff, MARCH_STORE_AUX);
 }
 
 // Coordinate c in [-2, n + 1] of an axis with n nodes, mapped to the node
@@ -312,7 +331,7 @@ __global__ void __launch_bounds__(MW * MWPB) k_march(const T* __restrict__ fin, 
     const bool out = lane >= 2 && lane < MW - 2 && x < a.x1;
     const int yb = a.y0 + band * a.m_rows, ye = min(yb + a.m_rows, a.y1);
     const unsigned bytes = (unsigned)(NQ * a.plane * (long)sizeof(T));
-    if (band & 1) {
+    if (MARCH_ALTERNATE && (band & 1)) {
         Marcher<LIM, T, -1> mr(&a, fin, fout, bytes, x, out);
         mr.walk(yb, ye);
     } else {
@@ -328,14 +347,15 @@ inline bool march_fits(const StepArgs& a)
     return (double)NQ * (double)a.plane * (double)sizeof(T) < 2147483648.0;
 }
 
-// Strips, bands and rows per band: as many bands as keep every wavefront of
-// the launch resident at once (capacity_waves), but at least MRMIN rows per
-// band unless the grid has fewer rows.
-inline void set_march(StepArgs& a, long capacity_waves)
+// Strips, bands and rows per band: as many bands as give the launch the
+// fraction `frac` of the wavefronts the device holds at once
+// (capacity_waves), but at least MRMIN rows per band unless the grid has
+// fewer rows.
+inline void set_march(StepArgs& a, long capacity_waves, double frac)
 {
     const int ex = a.x1 - a.x0, ey = a.y1 - a.y0;
     a.m_nsx = (ex + MOUT - 1) / MOUT;
-    long nby = capacity_waves / (a.m_nsx > 0 ? a.m_nsx : 1);
+    long nby = (long)(frac * (double)capacity_waves) / (a.m_nsx > 0 ? a.m_nsx : 1);
     nby = std::max(1L, std::min(nby, (long)((ey + MRMIN - 1) / MRMIN)));
     a.m_rows = (int)((ey + nby - 1) / nby);
     if (a.m_rows < 1) a.m_rows = 1;
@@ -398,7 +418,7 @@ __global__ void __launch_bounds__(MW * MWPB) k_march_batch(const BatchSlot* __re
         const bool out = lane >= 2 && lane < MW - 2 && x < a.x1;
         const int yb = a.y0 + band * a.m_rows, ye = min(yb + a.m_rows, a.y1);
         const unsigned bytes = (unsigned)(NQ * a.plane * (long)sizeof(T));
-        if (band & 1) {
+        if (MARCH_ALTERNATE && (band & 1)) {
             Marcher<LIM, T, -1> mr(&a, fin, fout, bytes, x, out);
             mr.walk(yb, ye);
         } else {

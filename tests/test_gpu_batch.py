@@ -205,3 +205,25 @@ def test_nonfinite_slot_is_isolated(lib):
         for k in (0, 2, 3):
             assert np.array_equal(ref[k], b.get_f(sb[k]))
         b.status()      # cleared
+
+
+def test_riemann_batch_subset_matches_oracle(lib, orc):
+    # 16 instances of the seeded 512-instance batch, evenly spread over the
+    # sizes of those with at most 20000 nodes (so the oracle finishes in
+    # seconds), FP32 storage, autotuned classes, 40 steps
+    cases, _ = W.riemann_batch(n=512, precision="fp32")
+    small = sorted((c for c in cases if c["params"]["nx"] * c["params"]["ny"] <= 20000),
+                   key=lambda c: c["params"]["nx"] * c["params"]["ny"])
+    cases = [small[round(i * (len(small) - 1) / 15)] for i in range(16)]
+    n = 40
+    with lib.Batch(len(cases), precision="fp32") as b:
+        slots = add_all(b, cases)
+        b.autotune()
+        b.step(n)
+        b.status()
+        for c, s in zip(cases, slots):
+            p64 = dict(c["params"], precision="fp64")
+            fo = orc.run(p64, c["rho"], c["ux"], c["uy"], c["T"], n)
+            mo = orc.macros(p64, fo)
+            gamma = (c["params"]["b"] + 2.0) / c["params"]["b"]
+            assert_parity(b.macros(s), mo, TOL["fp32"], gamma, f"{c['name']} {c['params']['nx']}x{c['params']['ny']}")
