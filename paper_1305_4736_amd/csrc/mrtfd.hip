@@ -192,11 +192,13 @@ int mrtfd_create(const mrtfd_params* p, void* hip_stream, mrtfd_t* out)
     h->stream = (hipStream_t)hip_stream;
     h->L = layout_of(*p);
     for (int k = 0; k < 2; ++k) {
-        if (hipMalloc(&h->buf[k], h->L.buf_bytes) != hipSuccess) {
+        const hipError_t e = hipMalloc(&h->buf[k], h->L.buf_bytes);
+        if (e != hipSuccess) {
             (void)hipGetLastError();
             if (k == 1) (void)hipFree(h->buf[0]);
             delete h;
-            return fail(MRTFD_ENOMEM, "cannot allocate 2 x %zu bytes of state", h->L.buf_bytes);
+            return fail(MRTFD_ENOMEM, "cannot allocate 2 x %zu bytes of state (%s)", h->L.buf_bytes,
+                        hipGetErrorString(e));
         }
     }
     if (!build_blocks(p->eta0, &h->blocks)) {

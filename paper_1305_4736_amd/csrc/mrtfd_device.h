@@ -46,11 +46,11 @@ struct Blocks {
 // Everything a step needs that is uniform over the grid.
 struct StepArgs {
     const Blocks* __restrict__ Bp;   // device copy of the blocks (read with scalar loads)
-    double s[NQ];
+    double rdt[NQ];             // -dt * s_k: relaxation rates scaled for the update
     double b, inv_b, dt;
     double nux[4], nuy[4];      // Courant numbers |v_ia| dt / d_a per group
     double cx[4], cy[4];        // (1 - nu) / 2 per group and axis
-    double k8, k9;              // s_8 / s_5 - 1, s_9 / s_5 - 1 (0 when the correction is off)
+    double c8dt, c9dt;          // -dt (s_8 / s_5 - 1), -dt (s_9 / s_5 - 1); 0 when the correction is off
     double inv2dx, inv2dy;
     double side[4][4];          // (rho, ux, uy, T) of each side: equilibrium ghosts, walls
     int nx, ny;
@@ -266,9 +266,11 @@ __device__ __forceinline__ void velocity_of(const BT& B, const double* f, double
 // Limited jump psi(theta) * dn with theta = up / dn, in division-free and
 // branch-free form, equal to the printed piecewise limiter wherever theta is
 // defined and zero when the downstream jump vanishes:
-//   MC:     (sgn up + sgn dn) / 2 * min(2|up|, 2|dn|, |up + dn| / 2)
+//   MC:     (sgn up + sgn dn) * min(|up|, |dn|, |up + dn| / 4)
 //   minmod: (sgn up + sgn dn) / 2 * min(|up|, |dn|)
-// (opposite signs give zero; a zero jump makes the minimum zero).
+// (opposite signs give zero; a zero jump makes the minimum zero).  The MC
+// form is (sgn up + sgn dn) / 2 * min(2|up|, 2|dn|, |up + dn| / 2) with its
+// powers of two moved, which changes no bits.
 template <int LIM, typename R>
 __device__ __forceinline__ R limited(R up, R dn)
 {
@@ -277,34 +279,34 @@ __device__ __forceinline__ R limited(R up, R dn)
     } else if constexpr (LIM == 3) {    // first-order upwind
         return R(0);
     } else {
-        const R h = R(0.5) * (copysign(R(1), up) + copysign(R(1), dn));
+        const R h = copysign(R(1), up) + copysign(R(1), dn);
         const R au = fabs(up), ad = fabs(dn);
         if constexpr (LIM == 0)
-            return h * fmin(R(2) * fmin(au, ad), R(0.5) * fabs(up + dn));
+            return h * fmin(fmin(au, ad), R(0.25) * fabs(up + dn));
         else
-            return h * fmin(au, ad);
+            return R(0.5) * h * fmin(au, ad);
     }
 }
 
-// Convective increment of one population along one axis:
-//   -nu [ (f_J - f_{J-s}) + c (L(f_J - f_{J-s}, f_{J+s} - f_J) - L(f_{J-s} - f_{J-2s}, f_J - f_{J-s})) ]
+// Convective increment of one population along one axis, added to acc:
+//   acc - nu [ (f_J - f_{J-s}) + c (L(f_J - f_{J-s}, f_{J+s} - f_J) - L(f_{J-s} - f_{J-2s}, f_J - f_{J-s})) ]
 // with c = (1 - nu) / 2, s the sign of the velocity component.
-// (conv_increment is the last step, shared by every kernel so that all of
-// them round it alike; the library is built with contraction of a * b + c
-// only within one source expression.)
+// (conv_add is the last step, shared by every kernel so that all of them
+// round it alike; the library is built with contraction of a * b + c only
+// within one source expression.)
 template <typename R>
-__device__ __forceinline__ R conv_increment(R l1, R l0, R d1, R nu, R c)
+__device__ __forceinline__ R conv_add(R acc, R l1, R l0, R d1, R nu, R c)
 {
-    return -nu * fma(c, l1 - l0, d1);
+    return fma(-nu, fma(c, l1 - l0, d1), acc);
 }
 
 template <int LIM, typename R>
-__device__ __forceinline__ R conv1(R fm2, R fm1, R f0, R fp1, R nu, R c)
+__device__ __forceinline__ R conv1(R acc, R fm2, R fm1, R f0, R fp1, R nu, R c)
 {
     R d0 = fm1 - fm2, d1 = f0 - fm1, d2 = fp1 - f0;
     R l1 = limited<LIM>(d1, d2);
     R l0 = limited<LIM>(d0, d1);
-    return conv_increment(l1, l0, d1, nu, c);
+    return conv_add(acc, l1, l0, d1, nu, c);
 }
 
 }  // namespace mrtfd

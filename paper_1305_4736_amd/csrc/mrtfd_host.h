@@ -107,7 +107,7 @@ inline StepArgs make_args(const mrtfd_params& p, const Layout& L, const Blocks& 
     StepArgs a;
     std::memset(&a, 0, sizeof(a));
     a.Bp = blocks_dev;
-    for (int k = 0; k < NQ; ++k) a.s[k] = p.s[k];
+    for (int k = 0; k < NQ; ++k) a.rdt[k] = -p.dt * p.s[k];
     a.b = p.b;
     a.inv_b = 1.0 / p.b;
     a.dt = p.dt;
@@ -118,8 +118,8 @@ inline StepArgs make_args(const mrtfd_params& p, const Layout& L, const Blocks& 
         a.cy[g] = 0.5 * (1.0 - a.nuy[g]);
     }
     a.correction = p.energy_flux_correction ? 1 : 0;
-    a.k8 = a.correction ? p.s[7] / p.s[4] - 1.0 : 0.0;
-    a.k9 = a.correction ? p.s[8] / p.s[4] - 1.0 : 0.0;
+    a.c8dt = a.correction ? -p.dt * (p.s[7] / p.s[4] - 1.0) : 0.0;
+    a.c9dt = a.correction ? -p.dt * (p.s[8] / p.s[4] - 1.0) : 0.0;
     a.inv2dx = 0.5 / p.dx;
     a.inv2dy = 0.5 / p.dy;
     for (int s = 0; s < 4; ++s) {

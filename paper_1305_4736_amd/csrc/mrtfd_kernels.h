@@ -99,16 +99,14 @@ __device__ __forceinline__ void collision(const AT& a, const BT& B, const double
 #pragma unroll
     for (int k = 0; k < 4; ++k) w[k] = 0.0;
 #pragma unroll
-    for (int k = 4; k < NQ; ++k) w[k] = a.s[k] * (m[k] - eq[k]);
+    for (int k = 4; k < NQ; ++k) w[k] = a.rdt[k] * (m[k] - eq[k]);
     if (corr) {
         // energy-flux correction of moments 8 and 9 (central differences of u)
         const double div4b = 4.0 * a.inv_b * (dxux + dyuy);
         const double shear2 = 2.0 * (dxuy + dyux);
-        w[7] += a.k8 * P * (ux * (4.0 * dxux - div4b) + uy * shear2);
-        w[8] += a.k9 * P * (ux * shear2 + uy * (4.0 * dyuy - div4b));
+        w[7] += a.c8dt * P * (ux * (4.0 * dxux - div4b) + uy * shear2);
+        w[8] += a.c9dt * P * (ux * shear2 + uy * (4.0 * dyuy - div4b));
     }
-#pragma unroll
-    for (int k = 4; k < NQ; ++k) w[k] *= -a.dt;
     inverse_nc(B, w, coll);
 }
 
@@ -305,11 +303,11 @@ __device__ __forceinline__ void step_tile(const T* __restrict__ fin, T* __restri
         R acc = R(0);
         if (sgx(i) != 0) {
             const int sx = sgx(i);
-            acc += conv1<LIM, R>(tb[c0 - 2 * sx], tb[c0 - sx], f0, tb[c0 + sx], (R)a.nux[g], (R)a.cx[g]);
+            acc = conv1<LIM, R>(acc, tb[c0 - 2 * sx], tb[c0 - sx], f0, tb[c0 + sx], (R)a.nux[g], (R)a.cx[g]);
         }
         if (!FLAT && sgy(i) != 0) {
             const int sy = sgy(i) * TW;
-            acc += conv1<LIM, R>(tb[c0 - 2 * sy], tb[c0 - sy], f0, tb[c0 + sy], (R)a.nuy[g], (R)a.cy[g]);
+            acc = conv1<LIM, R>(acc, tb[c0 - 2 * sy], tb[c0 - sy], f0, tb[c0 + sy], (R)a.nuy[g], (R)a.cy[g]);
         }
         fout[(long)i * a.plane + n0] = (T)((double)f0 + (double)acc + coll[i]);
     }

@@ -206,7 +206,7 @@ struct Marcher {
             const R d1 = f0 - fm1, d2 = fp1 - f0;
             const R l1 = limited<LIM, R>(d1, d2);
             const R l0 = (sx > 0) ? lane_move<FROM_LEFT>(l1) : lane_move<FROM_RIGHT>(l1);
-            acc += conv_increment(l1, l0, d1, (R)a.nux[g], (R)a.cx[g]);
+            acc = conv_add(acc, l1, l0, d1, (R)a.nux[g], (R)a.cx[g]);
         }
         if (sy != 0) {
             R d1, l1, l0;
@@ -221,7 +221,7 @@ struct Marcher {
                 l0 = limited<LIM, R>(fD[i] - fE[i], d1);
                 carry[i] = l0;
             }
-            acc += conv_increment(l1, l0, d1, (R)a.nuy[g], (R)a.cy[g]);
+            acc = conv_add(acc, l1, l0, d1, (R)a.nuy[g], (R)a.cy[g]);
         }
         return (T)((double)f0 + (double)acc + coll[i]);
     }
