@@ -140,6 +140,26 @@ def cpu_baseline(log, nsteps=2):
                       f"(gcc -O2), {dt:.1f} s"}
 
 
+def run_limiters(log, steps=100):
+    """Step time of the march kernel with each limiter (the same workload,
+    FP64): MC, minmod, Lax-Wendroff (psi = 1), first-order upwind (psi = 0)."""
+    import torch
+
+    from paper_1305_4736_amd import mrtfd, workloads as W
+
+    out = {}
+    for lim in ("mc", "minmod", "lw", "upwind"):
+        case = W.shock_interface(precision="fp64", limiter=lim)
+        s = mrtfd.Solver(case["params"], stream=torch.cuda.current_stream())
+        s.init(case["rho"], case["ux"], case["uy"], case["T"])
+        s.step(10)
+        out[lim] = s.step_timed(steps) / steps
+        s.sync()
+        s.close()
+    log("[bench] limiters (fp64 ms/step): " + ", ".join(f"{k} {v:.4f}" for k, v in out.items()))
+    return out
+
+
 def run_batched(steps, warmup, log, n=512):
     """512 independent Riemann instances (log-uniform Nx in [128, 4096], Ny in
     [1, 256], seeded states) in one batch, FP32 storage, autotuned shape
@@ -212,6 +232,7 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--pmc-copy-calibration", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-limiters", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=8.0)
     ap.add_argument("--serve-rate", type=float, default=200.0)
@@ -248,6 +269,9 @@ def main():
         extra["fp32_storage"] = {"value": r32["value"], "ms_per_step": r32["ms_per_step"],
                                  "roofline_frac": rl32["frac"], "achieved_GBs": rl32["achieved"],
                                  "speedup_vs_fp64": r32["value"] / res["value"]}
+
+    if not args.no_limiters:
+        extra["limiters_fp64_ms_per_step"] = run_limiters(log)
 
     if not args.no_batched:
         extra["batched"] = run_batched(max(args.steps // 2, 20), 5, log)

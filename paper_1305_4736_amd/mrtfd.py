@@ -22,6 +22,15 @@ if not os.path.exists(LIB_PATH):
         f"{LIB_PATH} is missing: build it with `python -m paper_1305_4736_amd.build` "
         "(there is no CPU fallback)")
 
+# The library needs a HIP runtime (libamdhip64.so.7).  PyTorch ships its own
+# under that name; load it first when it is installed, so that the process
+# holds one HIP runtime that both use (a second copy would bring its own
+# device contexts and streams).
+try:
+    import torch  # noqa: F401
+except ImportError:
+    pass
+
 _lib = ctypes.CDLL(LIB_PATH)
 
 LIMITERS = {"mc": 0, "minmod": 1, "lw": 2, "upwind": 3}
