@@ -214,7 +214,7 @@ int mrtfd_batch_shape(mrtfd_batch_t b, int slot, int* txw, int* byr);
 /* Shape classes of a slot: 0..3 are LDS tiles of 256 nodes (32 x 8, 64 x 4,
  * 128 x 2, and 256 x 1 for one-row instances whose y sides are periodic or
  * outflow); 4 is the row-marching form (one wavefront per strip of 60
- * columns and band of up to 32 rows; instances whose state buffer is below
+ * columns and band of up to 12 rows; instances whose state buffer is below
  * 2 GiB).  All classes give bitwise identical results.  Force a slot into
  * class `shape` (for tuning and comparison); the slot's state is kept.
  * MRTFD_EINVAL for an unknown class or one that does not fit the slot. */

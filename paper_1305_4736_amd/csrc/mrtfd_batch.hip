@@ -11,7 +11,7 @@
 // a slot's result does not depend on which other slots share its launches.
 //
 // Shape classes: the row-marching strips of mrtfd_march.h (60 output
-// columns x bands of up to 32 rows per wavefront), and LDS tiles of 256
+// columns x bands of up to 12 rows per wavefront), and LDS tiles of 256
 // threads: 32 x 8, 64 x 4, 128 x 2, and 256 x 1 rows for one-row instances.
 // Each slot gets the class with the smallest estimated cost (work units x
 // cost per unit; a unit is a tile, or one row of a strip including the halo

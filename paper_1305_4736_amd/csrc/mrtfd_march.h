@@ -26,7 +26,10 @@ namespace {
 
 constexpr int MW = 64;           // lanes of a wavefront = columns of a strip
 constexpr int MOUT = MW - 4;     // output columns of a strip
-constexpr int MWPB = 4;          // wavefronts (independent strips) per block
+#ifndef MARCH_WPB
+#define MARCH_WPB 4
+#endif
+constexpr int MWPB = MARCH_WPB;  // wavefronts (independent strips) per block
 constexpr int MRMIN = 8;         // fewest rows per band when the grid is small
 #ifndef MARCH_PF
 #define MARCH_PF 1               // rows between issuing a row's loads and first using it
@@ -368,7 +371,13 @@ inline void set_march(StepArgs& a, long capacity_waves, double frac)
 
 namespace {
 
-constexpr int MBROWS = 32;       // rows per band of a batched instance
+// Rows per band of a batched instance: short bands balance the static
+// assignment of items to wavefronts over instances of mixed sizes (8-12
+// rows measured best on a 512-instance mix; 32 rows cost 19 % more).
+#ifndef MARCH_BROWS
+#define MARCH_BROWS 12
+#endif
+constexpr int MBROWS = MARCH_BROWS;
 
 // Band layout of a batched instance: bands of at most MBROWS rows.
 inline void set_march_rows(StepArgs& a, int rows)
