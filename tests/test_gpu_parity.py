@@ -241,3 +241,27 @@ def test_shock_interface_full_size_windows(lib, orc, precision):
         gw = tuple(sl(m)[ys, xs] for m in mg)
         ow = tuple(m[ys, xs] for m in mo)
         assert_parity(gw, ow, TOL[precision], 1.4, f"window x0={x0} y0={y0}")
+
+
+def test_state_buffers_of_2gib_and_more_use_the_tile_form(lib, orc):
+    # a 4096 x 4200 FP64 grid holds 2.2 GB per state buffer: beyond the
+    # row-marching form's 31-bit offsets, so the step runs the LDS-tile form
+    nsteps = 6
+    case = W.shock_interface(nx=4096, ny=4200, x_shock=0.5, x_int=0.7, nsteps=nsteps)
+    ny, nx = case["rho"].shape
+    print(f"[parity] shock_interface {nx}x{ny} fp64 {nsteps} steps (tile form)", flush=True)
+    with lib.Solver(case["params"]) as s:
+        s.init(case["rho"], case["ux"], case["uy"], case["T"])
+        s.step(nsteps)
+        s.sync()
+        mg = s.macros()
+    margin = 2 * nsteps + 2
+    for x0, y0 in [(0, 100), (2030, 7), (2880, 4200 - 40), (4096 - 80, 3000)]:
+        nxw, nyw = 80, 80
+        p, sl = _window_case(case, x0, nxw, y0, nyw)
+        fo = orc.run(p, sl(case["rho"]), sl(case["ux"]), sl(case["uy"]), sl(case["T"]), nsteps)
+        mo = orc.macros(p, fo)
+        xs = slice(0 if x0 == 0 else margin, nxw if x0 + nxw == nx else nxw - margin)
+        ys = slice(margin, nyw - margin)
+        assert_parity(tuple(sl(m)[ys, xs] for m in mg), tuple(m[ys, xs] for m in mo), TOL["fp64"], 1.4,
+                      f"window x0={x0} y0={y0}")
