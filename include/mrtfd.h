@@ -107,9 +107,13 @@ int mrtfd_footprint(const mrtfd_params* p, size_t* bytes);
 int mrtfd_init(mrtfd_t h, const double* rho, const double* ux, const double* uy,
                const double* T, int on_device);
 
-/* Advance by nsteps explicit stages; one fused kernel launch per step
- * (moments, equilibria, correction, collision, limited fluxes, update and
- * boundary fill).  Asynchronous on the handle's stream. */
+/* Advance by nsteps explicit stages (Sec. III update eq., every term at
+ * level n): one fused kernel launch per step computes moments, equilibria,
+ * correction, collision, limited fluxes and the update (the row-marching
+ * form for state buffers below 2 GiB, else the LDS-tile form; both give the
+ * same bits), followed by a small launch that refills NEE walls if there
+ * are any.  Asynchronous on the handle's stream; non-finite or unphysical
+ * nodes are flagged on the device and reported by mrtfd_sync. */
 int mrtfd_step(mrtfd_t h, long nsteps);
 
 /* As mrtfd_step, and report the elapsed device time of those launches in

@@ -32,14 +32,24 @@ from . import workloads as W
 
 
 class Server:
+    """`batch_factory(capacity, precision, limiter)`, `memory` = (free, total)
+    bytes and `materialize(spec)` replace the library batches, the device
+    memory query and the device-side field construction (scheduling tests run
+    them on the host)."""
+
     def __init__(self, capacity=2048, steps_per_tick=50, reserve_bytes=8 << 30, max_resident_bytes=None,
-                 limiter="mc", stream=None, keep_results=False):
-        import torch
-        self.torch = torch
-        self.device = torch.device("cuda", torch.cuda.current_device())
-        self.stream = stream if stream is not None else torch.cuda.current_stream()
-        self.batches = {p: mrtfd.Batch(capacity, precision=p, limiter=limiter, stream=self.stream)
-                        for p in ("fp32", "fp64")}
+                 limiter="mc", stream=None, keep_results=False, batch_factory=None, memory=None,
+                 materialize=None):
+        if batch_factory is None:
+            import torch
+            device = torch.device("cuda", torch.cuda.current_device())
+            self.stream = stream if stream is not None else torch.cuda.current_stream()
+            batch_factory = lambda cap, prec, lim: mrtfd.Batch(cap, precision=prec, limiter=lim, stream=self.stream)
+            if materialize is None:
+                materialize = lambda spec: W.materialize(spec, torch, device=device)
+        self.materialize = materialize if materialize is not None else W.materialize
+        self.memory = memory
+        self.batches = {p: batch_factory(capacity, p, limiter) for p in ("fp32", "fp64")}
         self.capacity = capacity
         self.k = int(steps_per_tick)
         self.reserve = int(reserve_bytes)
@@ -60,9 +70,8 @@ class Server:
         """Serve [(arrival_s, spec), ...] (sorted).  With realtime=False every
         request arrives at t = 0.  Returns a report dict (and results if
         keep_results)."""
-        torch = self.torch
         reqs = sorted(stream_reqs, key=lambda r: r[0])
-        free0, total = mrtfd.device_memory()
+        free0, total = self.memory if self.memory is not None else mrtfd.device_memory()
         budget = free0 - self.reserve
         if self.cap_bytes is not None:
             budget = min(budget, int(self.cap_bytes))
@@ -97,8 +106,7 @@ class Server:
                         keep.append(i)
                         continue
                     b = self.batches[p["precision"]]
-                    fields = W.materialize(spec, torch, device=self.device)
-                    slot = b.add(p, *fields, nsteps=spec["nsteps"])
+                    slot = b.add(p, *self.materialize(spec), nsteps=spec["nsteps"])
                     active[(p["precision"], slot)] = {"i": i, "t": t_arr if realtime else 0.0, "fp": fp,
                                                       "nodes": p["nx"] * p["ny"], "steps": spec["nsteps"]}
                     resident += fp

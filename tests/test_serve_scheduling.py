@@ -1,0 +1,141 @@
+"""Host-side tests of the serving scheduler (paper_1305_4736_amd/serve.py)
+with a stand-in for the library's batches: first come, first served within a
+precision, the memory budget never exceeded and never overtaken, a full batch
+letting the other precision pass, every request stepped exactly its budget,
+and every request answered once."""
+import pytest
+
+from paper_1305_4736_amd import mrtfd, serve
+from paper_1305_4736_amd import workloads as W
+
+
+class FakeBatch:
+    """Slots with step budgets; records admissions and the resident bytes."""
+
+    def __init__(self, capacity, precision, limiter, ledger):
+        self.capacity, self.precision = capacity, precision
+        self.slots = {}
+        self.ledger = ledger
+
+    def add(self, p, rho, ux, uy, T, nsteps):
+        assert rho.shape == (p["ny"], p["nx"])
+        k = min(set(range(self.capacity)) - set(self.slots))
+        self.slots[k] = {"left": nsteps, "done": 0, "fp": mrtfd.footprint(p), "nsteps": nsteps}
+        self.ledger["resident"] += self.slots[k]["fp"]
+        self.ledger["peak"] = max(self.ledger["peak"], self.ledger["resident"])
+        self.ledger["admitted"].append((self.precision, p["nx"], p["ny"], nsteps))
+        return k
+
+    def step(self, n):
+        for s in self.slots.values():
+            d = min(n, s["left"])
+            s["left"] -= d
+            s["done"] += d
+
+    def remaining(self, k):
+        return self.slots[k]["left"]
+
+    def steps_done(self, k):
+        return self.slots[k]["done"]
+
+    def macros(self, k):
+        return ("macros", self.precision, k)
+
+    def remove(self, k):
+        s = self.slots.pop(k)
+        assert s["done"] == s["nsteps"]
+        self.ledger["resident"] -= s["fp"]
+        self.ledger["finished"] += 1
+
+    def sync(self):
+        pass
+
+    def status(self):
+        pass
+
+    def close(self):
+        pass
+
+
+def make_server(capacity, budget, ledger, steps_per_tick=300):
+    factory = lambda cap, prec, lim: FakeBatch(cap, prec, lim, ledger)
+    return serve.Server(capacity=capacity, steps_per_tick=steps_per_tick, reserve_bytes=0, keep_results=True,
+                        batch_factory=factory, memory=(budget, 1 << 40))
+
+
+def small_stream(n, seed):
+    reqs = W.serve_stream(rate=1000.0, duration=10.0, seed=seed, log_lo=16, log_hi=48, max_requests=n)
+    assert len(reqs) == n
+    return reqs
+
+
+def ledger():
+    return {"resident": 0, "peak": 0, "admitted": [], "finished": 0}
+
+
+def key(spec):
+    p = spec["params"]
+    return (p["precision"], p["nx"], p["ny"], spec["nsteps"])
+
+
+def test_fifo_and_memory_budget():
+    reqs = small_stream(40, seed=5)
+    fps = [mrtfd.footprint(s["params"]) for _, s in reqs]
+    budget = 3 * sorted(fps)[len(fps) // 2]       # about three requests resident at a time
+    assert budget >= max(fps)
+    led = ledger()
+    with make_server(capacity=64, budget=budget, ledger=led) as srv:
+        rep = srv.run(reqs, realtime=False, drain=True)
+    assert rep["completed"] == rep["admitted"] == len(reqs) and rep["backlog"] == 0
+    assert led["finished"] == len(reqs) and led["resident"] == 0
+    assert led["peak"] <= budget and rep["max_resident_bytes"] <= budget
+    # no full batch: admissions follow arrival order across both precisions
+    assert led["admitted"] == [key(s) for _, s in reqs]
+    assert sorted(rep["results"]) == list(range(len(reqs)))
+    assert all(lat >= 0.0 for lat in (rep["p50_s"], rep["p99_s"]))
+
+
+def test_full_batch_lets_the_other_precision_pass():
+    reqs = small_stream(30, seed=11)
+    led = ledger()
+    with make_server(capacity=1, budget=1 << 40, ledger=led, steps_per_tick=100) as srv:
+        rep = srv.run(reqs, realtime=False, drain=True)
+    assert rep["completed"] == len(reqs) and led["finished"] == len(reqs)
+    assert rep["max_active"] <= 2
+    # first come, first served within each precision
+    for prec in ("fp32", "fp64"):
+        assert [a for a in led["admitted"] if a[0] == prec] == [key(s) for _, s in reqs
+                                                                 if s["params"]["precision"] == prec]
+    # a request waiting for its (full) batch does not hold back later
+    # requests of the other precision: some of them are admitted first
+    keys = [key(s) for _, s in reqs]
+    assert len(set(keys)) == len(keys)
+    pos = {k: n for n, k in enumerate(led["admitted"])}
+    passed = [(i, j) for i in range(len(keys)) for j in range(i + 1, len(keys))
+              if keys[i][0] != keys[j][0] and pos[keys[j]] < pos[keys[i]]]
+    assert passed
+
+
+def test_stop_at_end_of_arrivals_reports_backlog():
+    reqs = small_stream(20, seed=3)
+    fps = [mrtfd.footprint(s["params"]) for _, s in reqs]
+    led = ledger()
+    with make_server(capacity=64, budget=max(fps), ledger=led, steps_per_tick=1) as srv:
+        rep = srv.run(reqs, realtime=False, drain=False, duration=0.0)
+    # one admission round, one tick: requests are left waiting or resident
+    assert rep["completed"] + rep["resident_at_end"] + rep["backlog"] == len(reqs)
+    assert rep["backlog"] > 0
+
+
+@pytest.mark.parametrize("seed", [13054737])
+def test_request_recipe(seed):
+    reqs = W.serve_stream(rate=200.0, duration=2.0, seed=seed)
+    kinds = {s["kind"] for _, s in reqs}
+    precs = {s["params"]["precision"] for _, s in reqs}
+    assert kinds == {"quadrant", "couette"} and precs == {"fp32", "fp64"}
+    for t, s in reqs:
+        p = s["params"]
+        assert 0.0 <= t < 2.0 and 64 <= p["nx"] <= 2048 and 64 <= p["ny"] <= 2048
+        assert 200 <= s["nsteps"] <= 5000
+    ts = [t for t, _ in reqs]
+    assert ts == sorted(ts) and 300 <= len(reqs) <= 500     # Poisson, mean 400
