@@ -318,8 +318,14 @@ struct Marcher {
 // items); items are numbered band after band, strip by strip within a band.
 // Adjacent bands march in opposite directions, so the halo rows two bands
 // share are read by both at about the same time.
+#ifndef MARCH_MINW32
+#define MARCH_MINW32 2           // wavefronts per SIMD the FP32 kernel must fit (register budget)
+#endif
+template <typename T>
+constexpr int march_min_waves() { return sizeof(T) == 4 ? MARCH_MINW32 : 1; }
+
 template <int LIM, typename T>
-__global__ void __launch_bounds__(MW * MWPB) k_march(const T* __restrict__ fin, T* __restrict__ fout,
+__global__ void __launch_bounds__(MW * MWPB, march_min_waves<T>()) k_march(const T* __restrict__ fin, T* __restrict__ fout,
                                                     const StepArgs* __restrict__ ap)
 {
     CArgs& a = *(CArgs*)ap;
