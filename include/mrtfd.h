@@ -225,10 +225,13 @@ int mrtfd_batch_shape(mrtfd_batch_t b, int slot, int* txw, int* byr);
 int mrtfd_batch_set_shape(mrtfd_batch_t b, int slot, int shape);
 
 /* Autotuner: measure the device time per work unit of each shape class (a
- * tile; a strip row including its bands' halo rows) on calibration
- * instances, write them to cost_per_unit_us[5] (may be NULL), and give
- * every slot the class with the smallest units x cost.  Slot states are
- * untouched; later additions use the measured costs. */
+ * tile; a strip row including its bands' halo rows) and of one small launch
+ * of it on calibration instances, write the former to cost_per_unit_us[5]
+ * (may be NULL), and give every slot the class with the smallest units x
+ * cost, except that a class whose slots together would save less than its
+ * launch costs leaves them in the strip class.  Slot states are untouched;
+ * later additions use the measured costs (a class not yet in use is charged
+ * its launch). */
 int mrtfd_batch_autotune(mrtfd_batch_t b, double* cost_per_unit_us);
 
 #ifdef __cplusplus

@@ -90,7 +90,8 @@ struct mrtfd_batch_s {
     int nlist[NSHAPE], nwall;
     bool dirty;
     long L;
-    double cost[NSHAPE];
+    double cost[NSHAPE];                // device microseconds per work unit of each class
+    double launch_us[NSHAPE];           // device microseconds of one launch of a class, beside its work
     double* staging;
     size_t staging_bytes;
     hipEvent_t ev0, ev1;
@@ -111,13 +112,23 @@ int check_slot(mrtfd_batch_s* B, int k)
     return MRTFD_OK;
 }
 
+// Occupied slots in class s.
+int members(const mrtfd_batch_s* B, int s)
+{
+    int n = 0;
+    for (int k = 0; k < B->capacity; ++k) n += (B->used[k] && B->shape[k] == s);
+    return n;
+}
+
+// Class of a new slot: the smallest estimated device time per step, where a
+// class with no slot yet also pays for its launch.
 int pick_shape(const mrtfd_batch_s* B, const mrtfd_params& p)
 {
     int best = 0;
     double best_cost = 1e300;
     for (int s = 0; s < NSHAPE; ++s) {
         if (!shape_fits(p, s)) continue;
-        const double c = (double)tiles_of(p, s) * B->cost[s];
+        const double c = (double)tiles_of(p, s) * B->cost[s] + (members(B, s) ? 0.0 : B->launch_us[s]);
         if (c < best_cost) {
             best_cost = c;
             best = s;
@@ -351,7 +362,10 @@ int mrtfd_batch_create(int capacity, int precision, int limiter, void* hip_strea
     B->blk.resize(capacity);
     B->used.assign(capacity, 0);
     B->shape.assign(capacity, 0);
-    for (int s = 0; s < NSHAPE; ++s) B->cost[s] = DEFAULT_COST[s];
+    for (int s = 0; s < NSHAPE; ++s) {
+        B->cost[s] = DEFAULT_COST[s];
+        B->launch_us[s] = 10.0;
+    }
     const size_t lists = (size_t)(NSHAPE * (capacity + 1) + NSHAPE * capacity + capacity) * sizeof(int);
     if (hipMalloc(&B->d_slot, capacity * sizeof(BatchSlot)) != hipSuccess ||
         hipMalloc(&B->d_blocks, capacity * sizeof(Blocks)) != hipSuccess ||
@@ -655,15 +669,16 @@ int mrtfd_batch_set_shape(mrtfd_batch_t B, int k, int shape)
 // instances (a 2-D grid for the strips and the three 2-D tiles, a one-row
 // grid for the row tile), then give every occupied slot the cheapest class.
 // Slot states are untouched.
-int mrtfd_batch_autotune(mrtfd_batch_t B, double* cost_per_tile_us)
+int mrtfd_batch_autotune(mrtfd_batch_t B, double* cost_per_unit_us)
 {
     if (!B) return fail(MRTFD_EINVAL, "NULL batch");
     HIPCHK(hipStreamSynchronize(B->stream));
-    for (int s = 0; s < NSHAPE; ++s) {
+    // time `steps` launches of one calibration instance forced into class s
+    auto time_class = [&](int s, int nx, int ny, int steps, double* ms) -> int {
         mrtfd_params p;
         std::memset(&p, 0, sizeof(p));
-        p.nx = SHAPES[s].flat ? 262144 : 2048;
-        p.ny = SHAPES[s].flat ? 1 : 512;
+        p.nx = nx;
+        p.ny = ny;
         p.dx = p.dy = 1.0 / 512;
         p.dt = 0.05 * p.dx / 6.0;
         p.eta0 = 2.5;
@@ -676,23 +691,63 @@ int mrtfd_batch_autotune(mrtfd_batch_t B, double* cost_per_tile_us)
         mrtfd_batch_t C = nullptr;
         int rc = mrtfd_batch_create(1, B->precision, B->limiter, B->stream, &C);
         if (rc) return rc;
-        for (int q = 0; q < NSHAPE; ++q) C->cost[q] = (q == s) ? 1.0 : 1e30;   // force shape s
         const size_t n = (size_t)p.nx * p.ny;
         std::vector<double> one(n, 1.0), zero(n, 0.0);
         int k = -1;
         rc = mrtfd_batch_add(C, &p, one.data(), zero.data(), zero.data(), one.data(), 0, -1, &k);
-        double ms = 0.0;
+        if (!rc) rc = assign_shape(C, k, s);
         if (!rc) rc = mrtfd_batch_step(C, 3);
-        if (!rc) rc = mrtfd_batch_step_timed(C, 20, &ms);
-        const long tiles = tiles_of(p, s);
+        if (!rc) rc = mrtfd_batch_step_timed(C, steps, ms);
         mrtfd_batch_destroy(C);
+        return rc;
+    };
+    for (int s = 0; s < NSHAPE; ++s) {
+        const bool flat = SHAPES[s].flat;
+        const int nx = flat ? 262144 : 2048, ny = flat ? 1 : 512;
+        double ms = 0.0, ms0 = 0.0;
+        int rc = time_class(s, nx, ny, 20, &ms);
+        if (!rc) rc = time_class(s, flat ? 256 : 16, flat ? 1 : 16, 20, &ms0);   // one small launch
         if (rc) return rc;
-        B->cost[s] = 1e3 * ms / 20.0 / (double)tiles;   // microseconds per work unit
-        if (cost_per_tile_us) cost_per_tile_us[s] = B->cost[s];
+        mrtfd_params p;
+        std::memset(&p, 0, sizeof(p));
+        p.nx = nx;
+        p.ny = ny;
+        for (int q = 0; q < 4; ++q) p.bc[q].kind = MRTFD_BC_PERIODIC;
+        B->launch_us[s] = 1e3 * ms0 / 20.0;
+        B->cost[s] = std::max(1e3 * (ms - ms0) / 20.0, 1e-3) / (double)tiles_of(p, s);   // per work unit
+        if (cost_per_unit_us) cost_per_unit_us[s] = B->cost[s];
+    }
+    // every slot to its cheapest class by work; then a class whose slots
+    // together would save less than its launch costs returns them to the
+    // strips
+    std::vector<int> pick(B->capacity, -1);
+    for (int k = 0; k < B->capacity; ++k) {
+        if (!B->used[k]) continue;
+        double best = 1e300;
+        for (int s = 0; s < NSHAPE; ++s) {
+            if (!shape_fits(B->prm[k], s)) continue;
+            const double c = (double)tiles_of(B->prm[k], s) * B->cost[s];
+            if (c < best) {
+                best = c;
+                pick[k] = s;
+            }
+        }
+    }
+    for (int s = 0; s < NSHAPE; ++s) {
+        if (s == MARCH) continue;
+        double saving = 0.0;
+        for (int k = 0; k < B->capacity; ++k) {
+            if (pick[k] != s) continue;
+            if (!shape_fits(B->prm[k], MARCH)) saving = 1e300;   // no alternative
+            else saving += (double)tiles_of(B->prm[k], MARCH) * B->cost[MARCH] - (double)tiles_of(B->prm[k], s) * B->cost[s];
+        }
+        if (saving < B->launch_us[s])
+            for (int k = 0; k < B->capacity; ++k)
+                if (pick[k] == s) pick[k] = MARCH;
     }
     for (int k = 0; k < B->capacity; ++k) {
         if (!B->used[k]) continue;
-        int rc = assign_shape(B, k, pick_shape(B, B->prm[k]));
+        int rc = assign_shape(B, k, pick[k]);
         if (rc) return rc;
     }
     B->dirty = true;
