@@ -52,23 +52,29 @@ class _Params(ctypes.Structure):
 _lib = None
 
 
+def open_library(path: str):
+    """Open a build of mrtfd_oracle.c (the default one, or a variant the
+    tests compile with a planted mistake to check that the pins catch it)."""
+    lib = ctypes.CDLL(path)
+    dp = ctypes.POINTER(ctypes.c_double)
+    pp = ctypes.POINTER(_Params)
+    lib.orc_constants.argtypes = [ctypes.c_double, dp, dp, dp, dp]
+    lib.orc_feq_hat.argtypes = [ctypes.c_double] * 5 + [dp]
+    lib.orc_feq.argtypes = [ctypes.c_double] * 6 + [dp]
+    lib.orc_init.argtypes = [pp, dp, dp, dp, dp, dp]
+    lib.orc_advance.argtypes = [pp, dp, ctypes.c_long]
+    lib.orc_macros.argtypes = [pp, dp, dp, dp, dp, dp]
+    lib.orc_noneq.argtypes = [pp, dp, ctypes.c_int, dp]
+    assert lib.orc_sizeof_params() == ctypes.sizeof(_Params)
+    return lib
+
+
 def _load():
     global _lib
     if _lib is None:
         if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
             build(force=True)
-        lib = ctypes.CDLL(_LIB)
-        dp = ctypes.POINTER(ctypes.c_double)
-        pp = ctypes.POINTER(_Params)
-        lib.orc_constants.argtypes = [ctypes.c_double, dp, dp, dp, dp]
-        lib.orc_feq_hat.argtypes = [ctypes.c_double] * 5 + [dp]
-        lib.orc_feq.argtypes = [ctypes.c_double] * 6 + [dp]
-        lib.orc_init.argtypes = [pp, dp, dp, dp, dp, dp]
-        lib.orc_advance.argtypes = [pp, dp, ctypes.c_long]
-        lib.orc_macros.argtypes = [pp, dp, dp, dp, dp, dp]
-        lib.orc_noneq.argtypes = [pp, dp, ctypes.c_int, dp]
-        assert lib.orc_sizeof_params() == ctypes.sizeof(_Params)
-        _lib = lib
+        _lib = open_library(_LIB)
     return _lib
 
 

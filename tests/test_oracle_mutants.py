@@ -1,0 +1,86 @@
+"""The pins must be able to fail: each case plants one plausible mistake in a
+copy of the oracle's C source (a flipped sign, a dropped term, a wrong index
+or upwind side, transposed operands, a wrong breakpoint), builds it, and runs
+the oracle pins against it until one fails.  A mistake no pin catches fails
+the test.  Everything here runs on the CPU."""
+import os
+import subprocess
+
+import pytest
+
+import oracle
+import test_oracle_constants as T_const
+import test_oracle_invariants as T_inv
+import test_oracle_noneq as T_noneq
+import test_oracle_physics as T_phys
+import test_oracle_textbook as T_text
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "mrtfd_oracle.c")
+
+# (name, original text, planted mistake)
+MUTANTS = [
+    ("correction_8_sign", "R[7] += C8;", "R[7] -= C8;"),
+    ("correction_9_dropped", "R[8] += C9;", "R[8] += 0.0 * C9;"),
+    ("y_upwind_side", "int ex = (a == 0) ? sg : 0, ey = (a == 1) ? sg : 0;",
+     "int ex = (a == 0) ? sg : 0, ey = (a == 1) ? -sg : 0;"),
+    ("inflow_face_operands", "limited_jump(p->limiter, fJm2, fJm1, fJ);", "limited_jump(p->limiter, fJm1, fJm2, fJ);"),
+    ("courant_without_A", "double nu = p->dt / (C->A[i] * ((a == 0) ? p->dx : p->dy));",
+     "double nu = p->dt / ((a == 0) ? p->dx : p->dy);"),
+    ("temperature_factor", "double T = (fh[3] - (fh[1] * fh[1] + fh[2] * fh[2]) / rho) / (p->b * rho);",
+     "double T = (fh[3] - (fh[1] * fh[1] + fh[2] * fh[2]) / rho) / (2.0 * p->b * rho);"),
+    ("mc_breakpoint", "if (theta <= 1.0 / 3.0) return 2.0 * theta;", "if (theta <= 1.0 / 2.0) return 2.0 * theta;"),
+    ("minmod_cap", "if (theta <= 1.0) return theta;", "if (theta <= 1.0) return 1.0;"),
+    ("matrix_row_12_index", "out[11] = cx * dxy;", "out[11] = cy * dxy;"),
+    ("matrix_row_14_term", "out[13] = c2 * ce;", "out[13] = ce * ce;"),
+    ("eta_on_wrong_group", "C->eta[i] = (g == 0) ? eta0 : 0.0;", "C->eta[i] = (g == 1) ? eta0 : 0.0;"),
+    ("wall_density", "double rw = r1 * T1 / st[3];", "double rw = r1;"),
+]
+
+# the pins, cheapest first
+PINS = [
+    lambda o: T_const.test_velocity_set_matches_paper(o),
+    lambda o: T_const.test_inverse(o),
+    lambda o: T_const.test_first_rows_are_conserved_moments(o),
+    lambda o: T_const.test_seven_moment_relations(o, 5.0),
+    lambda o: T_const.test_feq_hat_consistent_with_velocity_space(o),
+    lambda o: T_const.test_eta_enters_only_through_m(o),
+    lambda o: T_inv.test_uniform_state_is_fixed_point(o),
+    lambda o: T_inv.test_conservation_periodic(o, "mc"),
+    lambda o: T_inv.test_rotation_symmetry(o),
+    lambda o: T_inv.test_mirror_symmetry(o),
+    lambda o: T_inv.test_boundaries_do_not_act_ahead_of_waves(o),
+    lambda o: T_noneq.test_zero_at_equilibrium(o),
+    lambda o: T_noneq.test_star_equals_plain_at_rest(o),
+    lambda o: T_text.test_unit_courant_is_exact_shift(o),
+    lambda o: T_text.test_reduces_to_textbook_limited_scheme(o, "lw"),
+    lambda o: T_text.test_reduces_to_textbook_limited_scheme(o, "minmod"),
+    lambda o: T_text.test_reduces_to_textbook_limited_scheme(o, "mc"),
+    lambda o: T_text.test_total_variation_diminishing(o, "mc"),
+    lambda o: T_phys.test_shear_wave_decay_rate_uses_s7(o),
+    lambda o: T_phys.test_sod_vs_exact(o, "mc"),
+    lambda o: T_phys.test_thermal_wave_decay_rate_uses_s8_s9(o),
+    lambda o: T_phys.test_couette_profiles_and_prandtl_effect(o),
+]
+
+
+@pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_a_pin_catches_the_planted_mistake(name, old, new, tmp_path):
+    src = open(SRC).read()
+    assert src.count(old) == 1, name
+    path_c = tmp_path / f"{name}.c"
+    path_so = tmp_path / f"lib{name}.so"
+    path_c.write_text(src.replace(old, new))
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", str(path_so), str(path_c), "-lm"])
+    saved = oracle._load()
+    oracle._lib = oracle.open_library(str(path_so))
+    caught = None
+    try:
+        for k, pin in enumerate(PINS):
+            try:
+                pin(oracle)
+            except (AssertionError, FloatingPointError, ValueError, ZeroDivisionError):
+                caught = k
+                break
+    finally:
+        oracle._lib = saved
+    assert caught is not None, f"no pin catches the planted mistake {name}"
