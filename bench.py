@@ -160,6 +160,25 @@ def run_limiters(log, steps=100):
     return out
 
 
+def run_small(log, steps=2000):
+    """Latency-bound small configurations, as device microseconds per step
+    (FP64): the 400 x 1 Sod tube and the 4 x 200 thermal Couette flow."""
+    import torch
+
+    from paper_1305_4736_amd import mrtfd, workloads as W
+
+    out = {}
+    for name, case in (("sod_400x1", W.sod()), ("couette_4x200_pr1", W.couette(pr=1.0))):
+        s = mrtfd.Solver(case["params"], stream=torch.cuda.current_stream())
+        s.init(case["rho"], case["ux"], case["uy"], case["T"])
+        s.step(100)
+        out[name] = 1e3 * s.step_timed(steps) / steps
+        s.sync()
+        s.close()
+    log("[bench] small configs (fp64 us/step): " + ", ".join(f"{k} {v:.2f}" for k, v in out.items()))
+    return out
+
+
 def run_batched(steps, warmup, log, n=512):
     """512 independent Riemann instances (log-uniform Nx in [128, 4096], Ny in
     [1, 256], seeded states) in one batch, FP32 storage, autotuned shape
@@ -272,6 +291,7 @@ def main():
 
     if not args.no_limiters:
         extra["limiters_fp64_ms_per_step"] = run_limiters(log)
+        extra["small_configs_fp64_us_per_step"] = run_small(log)
 
     if not args.no_batched:
         extra["batched"] = run_batched(max(args.steps // 2, 20), 5, log)

@@ -30,7 +30,14 @@ constexpr int MOUT = MW - 4;     // output columns of a strip
 #define MARCH_WPB 4
 #endif
 constexpr int MWPB = MARCH_WPB;  // wavefronts (independent strips) per block
-constexpr int MRMIN = 8;         // fewest rows per band when the grid is small
+// Fewest rows per band.  Small grids are bound by the latency of walking
+// the band row after row, so they get as many one-row bands as the device
+// holds (4 x 200: 10 us per step, against 25 us with 8-row bands); large
+// grids are limited by the resident wavefronts instead.
+#ifndef MARCH_RMIN
+#define MARCH_RMIN 1
+#endif
+constexpr int MRMIN = MARCH_RMIN;
 #ifndef MARCH_PF
 #define MARCH_PF 1               // rows between issuing a row's loads and first using it
 #endif
