@@ -54,8 +54,9 @@ struct StepArgs {
     double inv2dx, inv2dy;
     double side[4][4];          // (rho, ux, uy, T) of each side: equilibrium ghosts, walls
     int nx, ny;
-    long pitch;                 // elements per padded row
-    long plane;                 // elements per padded plane
+    long pitch;                 // element stride between rows of a plane
+    long plane;                 // element stride between planes
+    long elems;                 // elements of a state buffer
     long org;                   // element offset of node (0, 0) inside a plane
     int x0, x1, y0, y1;         // evolved node range [x0, x1) x [y0, y1)
     int ntx, nty;               // step-kernel tiles along x and y

@@ -36,9 +36,20 @@ inline int fail(int code, const char* fmt, ...)
             return fail(MRTFD_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));      \
     } while (0)
 
+// State layout: 16 planes of (ny + 4) padded rows.  With ROW_INTERLEAVED the
+// 16 planes of one row are adjacent (row stride 16 pitch, plane stride
+// pitch), otherwise each plane is contiguous (row stride pitch, plane stride
+// (ny + 4) pitch).  Kernels only use the two strides and the origin.
+#ifndef MRTFD_ROW_INTERLEAVED
+#define MRTFD_ROW_INTERLEAVED 1
+#endif
 struct Layout {
     size_t esize;
-    long pitch, plane, org;
+    long pitch;     // elements of one padded row of one plane
+    long row;       // element stride between consecutive rows of a plane
+    long plane;     // element stride between planes
+    long org;       // element offset of node (0, 0) in plane 0
+    long elems;     // elements of a buffer
     size_t buf_bytes;
 };
 
@@ -49,11 +60,18 @@ inline Layout layout_of(const mrtfd_params& p)
     const long line = 128 / (long)L.esize;   // elements per 128-byte line
     const long xoff = line;                  // x = 0 starts a line; ghosts sit before it
     L.pitch = ((xoff + p.nx + HALO + line - 1) / line) * line;
-    L.org = (long)HALO * L.pitch + xoff;
-    L.plane = (long)(p.ny + 2 * HALO) * L.pitch;
-    L.buf_bytes = (size_t)NQ * L.plane * L.esize;
+    const long rows = (long)(p.ny + 2 * HALO);
+    L.row = MRTFD_ROW_INTERLEAVED ? NQ * L.pitch : L.pitch;
+    L.plane = MRTFD_ROW_INTERLEAVED ? L.pitch : rows * L.pitch;
+    L.org = (long)HALO * L.row + xoff;
+    L.elems = (long)NQ * rows * L.pitch;
+    L.buf_bytes = (size_t)L.elems * L.esize;
     return L;
 }
+
+// Largest element offset inside one plane's addressing (kernels form the
+// offset of a node within its plane in 32-bit integers).
+inline long plane_span(const Layout& L) { return MRTFD_ROW_INTERLEAVED ? L.elems : L.plane; }
 
 inline int validate(const mrtfd_params* p)
 {
@@ -95,8 +113,8 @@ inline int validate(const mrtfd_params* p)
     if (p->energy_flux_correction && !(p->s[4] > 0)) return fail(MRTFD_EINVAL, "the correction needs s_5 > 0");
     if (!(p->eta0 >= 0)) return fail(MRTFD_EINVAL, "eta0 must be >= 0");
     const Layout L = layout_of(*p);
-    if (L.plane >= (1L << 31))
-        return fail(MRTFD_EINVAL, "grid %d x %d too large: a padded plane must stay below 2^31 elements", p->nx, p->ny);
+    if (plane_span(L) >= (1L << 31))
+        return fail(MRTFD_EINVAL, "grid %d x %d too large: node offsets must stay below 2^31 elements", p->nx, p->ny);
     return MRTFD_OK;
 }
 
@@ -131,9 +149,10 @@ inline StepArgs make_args(const mrtfd_params& p, const Layout& L, const Blocks& 
     }
     a.nx = p.nx;
     a.ny = p.ny;
-    a.pitch = L.pitch;
+    a.pitch = L.row;
     a.plane = L.plane;
     a.org = L.org;
+    a.elems = L.elems;
     a.x0 = (p.bc[0].kind == BC_WALL);
     a.x1 = p.nx - (p.bc[1].kind == BC_WALL);
     a.y0 = (p.bc[2].kind == BC_WALL);

@@ -346,7 +346,7 @@ __global__ void __launch_bounds__(MW * MWPB, march_min_waves<T>()) k_march(const
     const int x = a.x0 + strip * MOUT - 2 + lane;
     const bool out = lane >= 2 && lane < MW - 2 && x < a.x1;
     const int yb = a.y0 + band * a.m_rows, ye = min(yb + a.m_rows, a.y1);
-    const unsigned bytes = (unsigned)(NQ * a.plane * (long)sizeof(T));
+    const unsigned bytes = (unsigned)(a.elems * (long)sizeof(T));
     if (MARCH_ALTERNATE && (band & 1)) {
         Marcher<LIM, T, -1> mr(&a, fin, fout, bytes, x, out);
         mr.walk(yb, ye);
@@ -360,7 +360,7 @@ __global__ void __launch_bounds__(MW * MWPB, march_min_waves<T>()) k_march(const
 template <typename T>
 inline bool march_fits(const StepArgs& a)
 {
-    return (double)NQ * (double)a.plane * (double)sizeof(T) < 2147483648.0;
+    return (double)a.elems * (double)sizeof(T) < 2147483648.0;
 }
 
 // Strips, bands and rows per band: as many bands as give the launch the
@@ -439,7 +439,7 @@ __global__ void __launch_bounds__(MW * MWPB) k_march_batch(const BatchSlot* __re
         const int x = a.x0 + strip * MOUT - 2 + lane;
         const bool out = lane >= 2 && lane < MW - 2 && x < a.x1;
         const int yb = a.y0 + band * a.m_rows, ye = min(yb + a.m_rows, a.y1);
-        const unsigned bytes = (unsigned)(NQ * a.plane * (long)sizeof(T));
+        const unsigned bytes = (unsigned)(a.elems * (long)sizeof(T));
         if (MARCH_ALTERNATE && (band & 1)) {
             Marcher<LIM, T, -1> mr(&a, fin, fout, bytes, x, out);
             mr.walk(yb, ye);
