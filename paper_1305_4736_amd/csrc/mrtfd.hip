@@ -191,28 +191,27 @@ int mrtfd_create(const mrtfd_params* p, void* hip_stream, mrtfd_t* out)
     h->p = *p;
     h->stream = (hipStream_t)hip_stream;
     h->L = layout_of(*p);
+    // every failure below releases what was set up so far through
+    // mrtfd_destroy (members start null; freeing null is a no-op)
     for (int k = 0; k < 2; ++k) {
         const hipError_t e = hipMalloc(&h->buf[k], h->L.buf_bytes);
         if (e != hipSuccess) {
             (void)hipGetLastError();
-            if (k == 1) (void)hipFree(h->buf[0]);
-            delete h;
-            return fail(MRTFD_ENOMEM, "cannot allocate 2 x %zu bytes of state (%s)", h->L.buf_bytes,
+            h->buf[k] = nullptr;
+            mrtfd_destroy(h);
+            return fail(MRTFD_ENOMEM, "cannot allocate 2 x %zu bytes of state (%s)", layout_of(*p).buf_bytes,
                         hipGetErrorString(e));
         }
     }
     if (!build_blocks(p->eta0, &h->blocks)) {
-        (void)hipFree(h->buf[0]);
-        (void)hipFree(h->buf[1]);
-        delete h;
+        mrtfd_destroy(h);
         return fail(MRTFD_EINVAL, "singular moment blocks for eta0 = %g", p->eta0);
     }
     if (hipMalloc(&h->flag, sizeof(int)) != hipSuccess || hipMalloc(&h->blocks_dev, sizeof(Blocks)) != hipSuccess ||
         hipMalloc(&h->args_dev, sizeof(StepArgs)) != hipSuccess ||
         hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess) {
-        (void)hipFree(h->buf[0]);
-        (void)hipFree(h->buf[1]);
-        delete h;
+        (void)hipGetLastError();
+        mrtfd_destroy(h);
         return fail(MRTFD_EDEVICE, "device set-up failed");
     }
     if (query_march_capacity(h) != MRTFD_OK) {
@@ -245,8 +244,8 @@ int mrtfd_destroy(mrtfd_t h)
     (void)hipFree(h->blocks_dev);
     (void)hipFree(h->args_dev);
     if (h->staging) (void)hipFree(h->staging);
-    (void)hipEventDestroy(h->ev0);
-    (void)hipEventDestroy(h->ev1);
+    if (h->ev0) (void)hipEventDestroy(h->ev0);
+    if (h->ev1) (void)hipEventDestroy(h->ev1);
     delete h;
     return MRTFD_OK;
 }

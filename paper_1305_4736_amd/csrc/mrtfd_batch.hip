@@ -395,19 +395,21 @@ int mrtfd_batch_create(int capacity, int precision, int limiter, void* hip_strea
 int mrtfd_batch_destroy(mrtfd_batch_t B)
 {
     if (!B) return MRTFD_OK;
-    (void)hipStreamSynchronize(B->stream);
+    // slot buffers come from the stream-ordered pool: return them on the
+    // batch's stream, then wait for it
     for (int k = 0; k < B->capacity; ++k)
         if (B->used[k]) {
-            (void)hipFree(B->slot[k].buf[0]);
-            (void)hipFree(B->slot[k].buf[1]);
+            (void)hipFreeAsync(B->slot[k].buf[0], B->stream);
+            (void)hipFreeAsync(B->slot[k].buf[1], B->stream);
         }
+    (void)hipStreamSynchronize(B->stream);
     (void)hipFree(B->d_slot);
     (void)hipFree(B->d_blocks);
     (void)hipFree(B->d_flags);
     (void)hipFree(B->d_lists);
     if (B->staging) (void)hipFree(B->staging);
-    (void)hipEventDestroy(B->ev0);
-    (void)hipEventDestroy(B->ev1);
+    if (B->ev0) (void)hipEventDestroy(B->ev0);
+    if (B->ev1) (void)hipEventDestroy(B->ev1);
     delete B;
     return MRTFD_OK;
 }
