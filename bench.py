@@ -17,8 +17,12 @@ Printed: ONE JSON line with the contract fields plus
   cpu_baseline -- the FP64 oracle on the host, on a bounded sample of the
                   same workload (a few full-grid steps)
   fp32_storage -- the same workload with f stored and convected in FP32
+  limiters_fp64_ms_per_step -- the FP64 step time with each limiter (MC,
+                  minmod, Lax-Wendroff, first-order upwind)
+  small_configs_fp64_us_per_step -- the latency-bound 400 x 1 Sod tube and
+                  4 x 200 thermal Couette flow, device microseconds per step
   batched      -- 512 independent Riemann instances of uneven size in one
-                  batch (FP32 storage, autotuned tile shapes)
+                  batch (FP32 storage, autotuned shape classes)
   served       -- a Poisson stream of solve requests (Riemann quadrants and
                   thermal Couette flows, 64..2048 per side, 200..5000 steps,
                   FP32 / FP64) served with continuous batching: p50 / p99
@@ -26,8 +30,8 @@ Printed: ONE JSON line with the contract fields plus
                   specified 200 requests/s (overloaded) and once at a
                   sustainable rate (drained).
 
-Options --pmc-copy-calibration and --no-cpu-baseline serve the profiling
-runs (see profiles/).
+Options --pmc-copy-calibration, --no-cpu-baseline, --no-limiters,
+--no-batched and --no-serve serve the profiling runs (see profiles/).
 """
 from __future__ import annotations
 
@@ -261,7 +265,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
-              "the multi-GPU decomposition is described in DESIGN.md but not built.", file=sys.stderr)
+              "a multi-GPU run (slabs along y with one halo exchange per step) is designed but not built.", file=sys.stderr)
         sys.exit(2)
 
     log = lambda m: print(m, file=sys.stderr, flush=True)
