@@ -10,12 +10,16 @@ inputs resident in HBM.
 
 Printed: ONE JSON line with the contract fields plus
   roofline     -- the step kernel's algorithmic HBM bytes per launch
-                  (16 reads + 16 writes of f per node) over its average
-                  launch time, measured with HIP events on the library's
-                  stream inside the timed region; traffic from the committed
+                  (16 reads + 16 writes of f per node-update; an FP64 launch
+                  takes two steps, i.e. two node-updates per node) over its
+                  average launch time, measured with HIP events on the
+                  library's stream inside the timed region; traffic (the HBM
+                  bytes the launch actually moves) from the committed
                   rocprofv3 counter summary when it matches the current kernel
   cpu_baseline -- the FP64 oracle on the host, on a bounded sample of the
                   same workload (a few full-grid steps)
+  fp64_one_step_per_launch -- the FP64 workload with one step per launch
+                  (the default takes two)
   fp32_storage -- the same workload with f stored and convected in FP32
   limiters_fp64_ms_per_step -- the FP64 step time with each limiter (MC,
                   minmod, Lax-Wendroff, first-order upwind)
@@ -31,7 +35,8 @@ Printed: ONE JSON line with the contract fields plus
                   sustainable rate (drained).
 
 Options --pmc-copy-calibration, --no-cpu-baseline, --no-limiters,
---no-batched and --no-serve serve the profiling runs (see profiles/).
+--no-batched, --no-serve and --steps-per-launch serve the profiling runs
+(see profiles/).
 """
 from __future__ import annotations
 
@@ -47,7 +52,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "node-updates/s (D2V16 MRT-FD) + % HBM peak; p50/p99 served-solve latency"
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_march_shock_interface_4096x1024.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_march2_shock_interface_4096x1024.json")
 
 
 def kernel_hash() -> str:
@@ -64,7 +69,7 @@ def algorithmic_bytes_per_node(precision: str) -> int:
     return 32 * (8 if precision == "fp64" else 4)
 
 
-def run_gpu(case, steps, warmup, noneq_every, log):
+def run_gpu(case, steps, warmup, noneq_every, log, per_launch=0):
     import torch
 
     from paper_1305_4736_amd import mrtfd
@@ -75,6 +80,8 @@ def run_gpu(case, steps, warmup, noneq_every, log):
     fields = [torch.tensor(case[k], dtype=torch.float64, device=dev) for k in ("rho", "ux", "uy", "T")]
     delta = torch.empty((16, ny, nx), dtype=torch.float64, device=dev) if noneq_every else None
     s = mrtfd.Solver(p, stream=torch.cuda.current_stream())
+    if per_launch:
+        s.steps_per_launch = per_launch
     s.init(*fields)
     del fields
     s.step(warmup)
@@ -102,6 +109,7 @@ def run_gpu(case, steps, warmup, noneq_every, log):
         "value": nodes * steps / elapsed,
         "kernel_ms_avg": kernel_ms / steps,
         "nodes": nodes,
+        "steps_per_launch": s.steps_per_launch,
     }
     s.close()
     del delta
@@ -112,18 +120,24 @@ def run_gpu(case, steps, warmup, noneq_every, log):
 
 
 def roofline(res, precision):
-    bytes_launch = algorithmic_bytes_per_node(precision) * res["nodes"]
-    achieved = bytes_launch / (res["kernel_ms_avg"] * 1e-3) / 1e9
+    # the step timer brackets whole chunks of launches; with two steps per
+    # launch (even chunks) a launch lasts two step-times and processes two
+    # node-updates per node
+    k = res["steps_per_launch"]
+    bytes_launch = algorithmic_bytes_per_node(precision) * res["nodes"] * k
+    launch_ms = res["kernel_ms_avg"] * k
+    achieved = bytes_launch / (launch_ms * 1e-3) / 1e9
+    kernel = "k_march2" if k == 2 else "k_march"
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
-        if t.get("kernel_hash") == kernel_hash() and t.get("precision") == precision:
+        if t.get("kernel_hash") == kernel_hash() and t.get("precision") == precision and t.get("kernel") == kernel:
             traffic = t["hbm_bytes_per_launch"]
     return {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "algorithmic_bytes_per_launch": bytes_launch, "kernel": "k_march",
-            "avg_launch_ms": round(res["kernel_ms_avg"], 5)}
+            "algorithmic_bytes_per_launch": bytes_launch, "kernel": kernel, "steps_per_launch": k,
+            "avg_launch_ms": round(launch_ms, 5)}
 
 
 def cpu_baseline(log, nsteps=2):
@@ -145,8 +159,9 @@ def cpu_baseline(log, nsteps=2):
 
 
 def run_limiters(log, steps=100):
-    """Step time of the march kernel with each limiter (the same workload,
-    FP64): MC, minmod, Lax-Wendroff (psi = 1), first-order upwind (psi = 0)."""
+    """Step time with each limiter (the same workload, FP64, the library's
+    default steps per launch): MC, minmod, Lax-Wendroff (psi = 1),
+    first-order upwind (psi = 0)."""
     import torch
 
     from paper_1305_4736_amd import mrtfd, workloads as W
@@ -251,6 +266,8 @@ def main():
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--noneq-every", type=int, default=100)
+    ap.add_argument("--steps-per-launch", type=int, default=0, choices=(0, 1, 2),
+                    help="force one or two steps per kernel launch (0: the library's default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--pmc-copy-calibration", action="store_true")
@@ -281,13 +298,20 @@ def main():
         copy_calibration(log)
 
     case = W.shock_interface(precision="fp64")
-    res = run_gpu(case, args.steps, args.warmup, args.noneq_every, log)
+    res = run_gpu(case, args.steps, args.warmup, args.noneq_every, log, args.steps_per_launch)
     rl = roofline(res, "fp64")
 
     extra = {}
+    if not args.steps_per_launch and res["steps_per_launch"] == 2:
+        # the same workload with one step per launch, for comparison
+        r1 = run_gpu(case, args.steps, args.warmup, args.noneq_every, log, 1)
+        rl1 = roofline(r1, "fp64")
+        extra["fp64_one_step_per_launch"] = {"value": r1["value"], "ms_per_step": r1["ms_per_step"],
+                                             "kernel_ms_per_step": round(r1["kernel_ms_avg"], 5),
+                                             "roofline_frac": rl1["frac"], "achieved_GBs": rl1["achieved"]}
     if not args.no_fp32:
         case32 = W.shock_interface(precision="fp32")
-        r32 = run_gpu(case32, args.steps, args.warmup, args.noneq_every, log)
+        r32 = run_gpu(case32, args.steps, args.warmup, args.noneq_every, log, args.steps_per_launch)
         rl32 = roofline(r32, "fp32")
         extra["fp32_storage"] = {"value": r32["value"], "ms_per_step": r32["ms_per_step"],
                                  "roofline_frac": rl32["frac"], "achieved_GBs": rl32["achieved"],

@@ -108,13 +108,28 @@ int mrtfd_init(mrtfd_t h, const double* rho, const double* ux, const double* uy,
                const double* T, int on_device);
 
 /* Advance by nsteps explicit stages (Sec. III update eq., every term at
- * level n): one fused kernel launch per step computes moments, equilibria,
- * correction, collision, limited fluxes and the update (the row-marching
- * form for state buffers below 2 GiB, else the LDS-tile form; both give the
- * same bits), followed by a small launch that refills NEE walls if there
- * are any.  Asynchronous on the handle's stream; non-finite or unphysical
- * nodes are flagged on the device and reported by mrtfd_sync. */
+ * level n): a fused kernel computes moments, equilibria, correction,
+ * collision, limited fluxes and the update.  With FP64 storage on grids
+ * large enough to fill the device (bands of at least 8 rows), where
+ * supported (no NEE wall side, state below 2 GiB), one launch takes two
+ * steps, the second reading
+ * the first's rows from on-chip memory, so the state crosses HBM once per
+ * two steps; an odd remainder, and handles set to one step per launch,
+ * take one launch per step (the row-marching form for state buffers below
+ * 2 GiB, else the LDS-tile form), followed by a small launch that refills
+ * NEE walls if there are any.  Every form gives the same bits.
+ * Asynchronous on the handle's stream; non-finite or unphysical nodes are
+ * flagged on the device and reported by mrtfd_sync. */
 int mrtfd_step(mrtfd_t h, long nsteps);
+
+/* Steps taken per kernel launch by mrtfd_step: k = 2 (the default for FP64
+ * storage on large grids, where supported) fuses pairs of steps, k = 1
+ * (the default otherwise) launches once per step.  Results are bitwise the same either
+ * way.  MRTFD_EINVAL for k other than 1 or 2,
+ * or k = 2 on a handle with a wall side or a state of 2 GiB or more (the
+ * setting is then unchanged). */
+int mrtfd_set_steps_per_launch(mrtfd_t h, int k);
+int mrtfd_get_steps_per_launch(mrtfd_t h, int* k);
 
 /* As mrtfd_step, and report the elapsed device time of those launches in
  * milliseconds, measured with HIP events on the handle's stream

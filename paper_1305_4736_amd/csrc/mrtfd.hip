@@ -44,6 +44,8 @@ struct mrtfd_s {
     bool ready;
     long steps;
     long march_capacity;    // wavefronts of the step kernel resident at once
+    long pair_capacity;     // pairs of the two-step kernel resident at once
+    int per_launch;         // steps per launch requested: 1, or 2 (fused pairs) where supported
     hipEvent_t ev0, ev1;
 };
 
@@ -55,6 +57,29 @@ void fill_args(mrtfd_s* h)
     h->args = make_args(h->p, h->L, h->blocks, h->blocks_dev, h->flag, f32 ? STEP_TXW32 : STEP_TXW64,
                         f32 ? STEP_BYR32 : STEP_BYR64, STEP_BAND);
     set_march(h->args, h->march_capacity, f32 ? MARCH_FRAC32 : MARCH_FRAC64);
+    set_pair(h->args, h->pair_capacity, MARCH2_FRAC);
+}
+
+// Whether this instance can take two steps per launch: the march form
+// (state below 2 GiB) and no walls (their refill sits between steps).
+bool pair_supported(const mrtfd_s* h)
+{
+    const StepArgs& a = h->args;
+    for (int s = 0; s < 4; ++s)
+        if (a.bc[s] == BC_WALL) return false;
+    const bool fits = (h->p.precision == MRTFD_FP32_STORAGE) ? march_fits<float>(a) : march_fits<double>(a);
+    return fits && a.x1 > a.x0 && a.y1 > a.y0;
+}
+
+template <typename T>
+const void* pair_kernel(int limiter)
+{
+    switch (limiter) {
+    case 0: return (const void*)k_march2<0, T>;
+    case 1: return (const void*)k_march2<1, T>;
+    case 2: return (const void*)k_march2<2, T>;
+    default: return (const void*)k_march2<3, T>;
+    }
 }
 
 template <typename T>
@@ -78,6 +103,11 @@ int query_march_capacity(mrtfd_s* h)
     HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, MW * MWPB, 0));
     h->march_capacity = (long)std::max(nb, 1) * MWPB * std::max(cus, 1);
+    const void* k2 = (h->p.precision == MRTFD_FP32_STORAGE) ? pair_kernel<float>(h->p.limiter)
+                                                             : pair_kernel<double>(h->p.limiter);
+    nb = 0;
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k2, 2 * MW, 0));
+    h->pair_capacity = (long)std::max(nb, 1) * std::max(cus, 1);
     return MRTFD_OK;
 }
 
@@ -142,6 +172,30 @@ int launch_step_t(mrtfd_s* h)
 int launch_step(mrtfd_s* h)
 {
     return (h->p.precision == MRTFD_FP32_STORAGE) ? launch_step_t<float>(h) : launch_step_t<double>(h);
+}
+
+// Two steps in one launch (pair_supported(h) holds).
+template <typename T>
+int launch_pair_t(mrtfd_s* h)
+{
+    const StepArgs& a = h->args;
+    const T* fin = (const T*)h->buf[h->cur];
+    T* fout = (T*)h->buf[1 - h->cur];
+    dim3 grid(8 * a.p_per_xcd), block(2 * MW);
+    switch (h->p.limiter) {
+    case 0: hipLaunchKernelGGL((k_march2<0, T>), grid, block, 0, h->stream, fin, fout, h->args_dev); break;
+    case 1: hipLaunchKernelGGL((k_march2<1, T>), grid, block, 0, h->stream, fin, fout, h->args_dev); break;
+    case 2: hipLaunchKernelGGL((k_march2<2, T>), grid, block, 0, h->stream, fin, fout, h->args_dev); break;
+    default: hipLaunchKernelGGL((k_march2<3, T>), grid, block, 0, h->stream, fin, fout, h->args_dev); break;
+    }
+    HIPCHK(hipGetLastError());
+    h->cur = 1 - h->cur;
+    return MRTFD_OK;
+}
+
+int launch_pair(mrtfd_s* h)
+{
+    return (h->p.precision == MRTFD_FP32_STORAGE) ? launch_pair_t<float>(h) : launch_pair_t<double>(h);
 }
 
 template <typename T>
@@ -219,6 +273,13 @@ int mrtfd_create(const mrtfd_params* p, void* hip_stream, mrtfd_t* out)
         return MRTFD_EDEVICE;
     }
     fill_args(h);
+    // Default: fused pairs for FP64 storage on grids whose pair bands hold
+    // at least MARCH2_MIN_ROWS rows.  A pair's band costs six more barrier
+    // iterations than rows, so short bands (small grids, bound by the
+    // latency of the walk) are faster one step per launch; FP32 storage
+    // gains nothing from fusing (its step is bound by its FP64 collision
+    // arithmetic, which fusing does not reduce).
+    h->per_launch = (pair_supported(h) && h->p.precision == MRTFD_FP64 && h->args.p_rows >= MARCH2_MIN_ROWS) ? 2 : 1;
     if (hipMemcpyAsync(h->blocks_dev, &h->blocks, sizeof(Blocks), hipMemcpyHostToDevice, h->stream) != hipSuccess ||
         hipMemcpyAsync(h->args_dev, &h->args, sizeof(StepArgs), hipMemcpyHostToDevice, h->stream) != hipSuccess) {
         mrtfd_destroy(h);
@@ -284,11 +345,34 @@ int mrtfd_step(mrtfd_t h, long nsteps)
     if (!h) return fail(MRTFD_EINVAL, "NULL handle");
     if (!h->ready) return fail(MRTFD_ESTATE, "mrtfd_step before mrtfd_init / mrtfd_set_f");
     if (nsteps < 0) return fail(MRTFD_EINVAL, "nsteps < 0");
-    for (long k = 0; k < nsteps; ++k) {
+    long k = 0;
+    if (h->per_launch == 2)
+        for (; k + 2 <= nsteps; k += 2) {
+            int rc = launch_pair(h);
+            if (rc) return rc;
+        }
+    for (; k < nsteps; ++k) {
         int rc = launch_step(h);
         if (rc) return rc;
     }
     h->steps += nsteps;
+    return MRTFD_OK;
+}
+
+int mrtfd_set_steps_per_launch(mrtfd_t h, int k)
+{
+    if (!h) return fail(MRTFD_EINVAL, "NULL handle");
+    if (k != 1 && k != 2) return fail(MRTFD_EINVAL, "steps per launch must be 1 or 2, got %d", k);
+    if (k == 2 && !pair_supported(h))
+        return fail(MRTFD_EINVAL, "two steps per launch need no wall sides and a state below 2 GiB");
+    h->per_launch = k;
+    return MRTFD_OK;
+}
+
+int mrtfd_get_steps_per_launch(mrtfd_t h, int* k)
+{
+    if (!h || !k) return fail(MRTFD_EINVAL, "NULL argument");
+    *k = h->per_launch;
     return MRTFD_OK;
 }
 

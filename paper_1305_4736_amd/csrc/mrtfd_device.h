@@ -64,6 +64,8 @@ struct StepArgs {
     int band;                   // tile columns per band of the XCD-aware order
     int m_nsx, m_nby, m_rows;   // row-marching form: strips, bands, rows per band
     int m_per_xcd;              // row-marching blocks per XCD slot
+    int p_nsx, p_nby, p_rows;   // two steps per pass: strips, bands and rows per band
+    int p_per_xcd;              // two steps per pass: blocks (pairs) per XCD slot
     int bc[4];                  // kinds of x-lo, x-hi, y-lo, y-hi
     int correction;
     int* flag;                  // set to 1 when a node is unphysical

@@ -17,6 +17,12 @@
 // remapped once per lane, a row once per row), so this kernel writes no
 // ghost images; equilibrium ghosts are constant and NEE walls are refilled
 // by a separate launch after the step.
+//
+// Two steps per pass (k_march2): a block holds two wavefronts on the same
+// strip and band.  The first takes step n -> n+1 from HBM and leaves each
+// new row in a ring of rows in LDS; the second takes step n+1 -> n+2 from
+// that ring and writes HBM.  A barrier per row keeps the two in step.  HBM
+// sees one read and one write of the state per two steps.
 #pragma once
 #include <algorithm>
 
@@ -40,6 +46,9 @@ constexpr int MWPB = MARCH_WPB;  // wavefronts (independent strips) per block
 constexpr int MRMIN = MARCH_RMIN;
 #ifndef MARCH_PF
 #define MARCH_PF 1               // rows between issuing a row's loads and first using it
+#endif
+#ifndef MARCH2_PF
+#define MARCH2_PF 2              // the same for the first step of a fused pair
 #endif
 #ifndef MARCH_LOAD_AUX
 #define MARCH_LOAD_AUX 0         // cache policy bits of the state loads
@@ -133,19 +142,74 @@ __device__ __forceinline__ int source_of(int c, int n, int lo_kind, int hi_kind)
     return c;
 }
 
+// Coordinate c in [-4, n + 3] mapped to the node whose value the first step
+// of a fused pair reads there: periodic sides wrap (any distance), outflow
+// sides repeat the last node, equilibrium sides keep their stored ghosts
+// (coordinates beyond the two ghost layers read the outer one; no output
+// the pair keeps depends on them).
+__device__ __forceinline__ int source_ext(int c, int n, int lo_kind, int hi_kind)
+{
+    if (c < 0) {
+        if (lo_kind == BC_PERIODIC) return ((c % n) + n) % n;
+        if (lo_kind == BC_OUTFLOW) return 0;
+        return max(c, -2);
+    }
+    if (c >= n) {
+        if (hi_kind == BC_PERIODIC) return c % n;
+        if (hi_kind == BC_OUTFLOW) return n - 1;
+        return min(c, n + 1);
+    }
+    return c;
+}
+
+// Coordinate c in [-2, n + 1] mapped to the node whose step result the
+// second step of a pair reads there: outflow ghosts repeat the last node
+// (its new value); periodic ghosts were computed by the first step at their
+// own lane or row, equilibrium ghosts passed through unchanged.
+__device__ __forceinline__ int source_out(int c, int n, int lo_kind, int hi_kind)
+{
+    if (c < 0 && lo_kind == BC_OUTFLOW) return 0;
+    if (c >= n && hi_kind == BC_OUTFLOW) return n - 1;
+    return c;
+}
+
+// Roles of a marching wavefront: one whole step (HBM to HBM), or the first
+// (HBM to LDS ring) or second (LDS ring to HBM) step of a fused pair.
+enum { ROLE_SINGLE = 0, ROLE_FIRST = 1, ROLE_SECOND = 2 };
+constexpr int PRING = 4;          // rows held by the ring of a pair
+constexpr int POUT = MW - 8;      // output columns of a pair's strip
+
+// The ring: row y of the first step's result lives in slot (y + 4) mod 4
+// (y >= -2), lane l of the strip at [slot][plane][l].
+template <typename T>
+struct PairRing {
+    T v[PRING][NQ][MW];
+};
+
 // One wavefront's walk through its band in direction DIR (+1: increasing y).
 // fB, fC, fD hold rows j - DIR, j, j + DIR of output row j and fE row
-// j + 2 DIR.  With MARCH_PF = 1 the loads of row j + 2 DIR are issued at the
-// start of row j; with MARCH_PF = 2 they were issued one row earlier and fF
+// j + 2 DIR.  With PF = 1 the loads of row j + 2 DIR are issued at the
+// start of row j; with PF = 2 they were issued one row earlier and fF
 // receives row j + 3 DIR while row j is computed.
-template <int LIM, typename T, int DIR>
+//
+// In a fused pair (ROLE_FIRST / ROLE_SECOND) the lanes of both wavefronts
+// are columns x0 + 56 s - 4 .. x0 + 56 s + 59 of strip s.  The first step
+// is valid on lanes 2..61, the second on lanes 4..59 (its output).
+template <int LIM, typename T, int DIR, int ROLE = ROLE_SINGLE>
 struct Marcher {
     using R = T;   // convection precision (FP64, or FP32 in FP32-storage mode)
+    // prefetch distance: the first step of a pair waits on HBM once per
+    // barrier-bound row, so it loads further ahead; the ring is close
+    static constexpr int PF = (ROLE == ROLE_FIRST) ? MARCH2_PF : (ROLE == ROLE_SECOND) ? 1 : MARCH_PF;
 
     CArgs* argp;                      // kernel arguments
     __amdgpu_buffer_rsrc_t rin, rout;
     unsigned vin;                     // per-lane load offset (bytes)
     unsigned vout;                    // per-lane store offset, NO_STORE off the output columns
+    PairRing<T>* ring;                // fused pair: the LDS ring
+    int lane;                         // ROLE_FIRST: own lane; ROLE_SECOND: lane read from the ring
+    bool pass;                        // ROLE_FIRST: an equilibrium ghost column (value passes through)
+    bool chk;                         // ROLE_FIRST: an interior column this wavefront checks
     T fB[NQ], fC[NQ], fD[NQ], fE[NQ], fF[NQ];
     double uxB, uyB, uxC, uyC, uxD, uyD, uxE, uyE;
     R carry[NQ];                      // limited jump of the y face carried from the previous row
@@ -155,8 +219,33 @@ struct Marcher {
           rin(__builtin_amdgcn_make_buffer_rsrc((void*)fin, (short)0, (int)bytes, BUF_WORD3)),
           rout(__builtin_amdgcn_make_buffer_rsrc((void*)fout, (short)0, (int)bytes, BUF_WORD3)),
           vin((unsigned)(source_of(min(x, ap->nx + 1), ap->nx, ap->bc[0], ap->bc[1]) + 2) * (unsigned)sizeof(T)),
-          vout(out ? (unsigned)(x + 2) * (unsigned)sizeof(T) : NO_STORE)
+          vout(out ? (unsigned)(x + 2) * (unsigned)sizeof(T) : NO_STORE), ring(nullptr), lane(0), pass(false),
+          chk(false)
     {
+    }
+
+    // A wavefront of a fused pair; l is its lane, x the lane's column.
+    __device__ __forceinline__ Marcher(CArgs* ap, const T* fin, T* fout, unsigned bytes, int x, int l,
+                                       PairRing<T>* rg)
+        : argp(ap),
+          rin(__builtin_amdgcn_make_buffer_rsrc((void*)fin, (short)0, (int)bytes, BUF_WORD3)),
+          rout(__builtin_amdgcn_make_buffer_rsrc((void*)fout, (short)0, (int)bytes, BUF_WORD3)), ring(rg)
+    {
+        const int nx = ap->nx, lo = ap->bc[0], hi = ap->bc[1];
+        if (ROLE == ROLE_FIRST) {
+            vin = (unsigned)(source_ext(x, nx, lo, hi) + 2) * (unsigned)sizeof(T);
+            vout = NO_STORE;
+            lane = l;
+            pass = (x < 0 && lo == BC_EQUIL) || (x >= nx && hi == BC_EQUIL);
+            chk = l >= 2 && l < MW - 2 && x >= ap->x0 && x < ap->x1;
+        } else {
+            vin = 0;
+            const bool out = l >= 4 && l < MW - 4 && x < ap->x1;
+            vout = out ? (unsigned)(x + 2) * (unsigned)sizeof(T) : NO_STORE;
+            lane = min(max(l + (source_out(x, nx, lo, hi) - x), 0), MW - 1);
+            pass = false;
+            chk = false;
+        }
     }
 
     // The kernel arguments, re-read at every row: hiding the pointer from the
@@ -171,9 +260,18 @@ struct Marcher {
 
     __device__ __forceinline__ void load(T (&dst)[NQ], int y, CArgs& a) const
     {
+        if (ROLE == ROLE_SECOND) {
+            // the first step's row (outflow ghost rows: the row they repeat)
+            const int ys = source_out(max(-2, min(y, a.ny + 1)), a.ny, a.bc[2], a.bc[3]);
+            const T(*src)[MW] = ring->v[(ys + 4) & (PRING - 1)];
+#pragma unroll
+            for (int i = 0; i < NQ; ++i) dst[i] = src[i][lane];
+            return;
+        }
         // rows beyond the ghost layers are only ever prefetched past a band's
         // end and never used: read the last ghost row instead
-        const int ys = source_of(max(-2, min(y, a.ny + 1)), a.ny, a.bc[2], a.bc[3]);
+        const int ys = (ROLE == ROLE_FIRST) ? source_ext(y, a.ny, a.bc[2], a.bc[3])
+                                            : source_of(max(-2, min(y, a.ny + 1)), a.ny, a.bc[2], a.bc[3]);
         const unsigned base = (unsigned)((a.org - 2 + (long)ys * a.pitch) * (long)sizeof(T));
         const unsigned pb = (unsigned)(a.plane * (long)sizeof(T));
 #pragma unroll
@@ -239,7 +337,7 @@ struct Marcher {
     __device__ __forceinline__ void row(int j)
     {
         CArgs& a = args();
-        if (MARCH_PF == 1)
+        if (PF == 1)
             load(fE, j + 2 * DIR, a);
         else
             load(fF, j + 3 * DIR, a);
@@ -266,29 +364,37 @@ struct Marcher {
             dyux = (uxp - uxm) * a.inv2dy;
             dyuy = (uyp - uym) * a.inv2dy;
         }
-        if (vout != NO_STORE && !(rho > 0.0 && P > 0.0)) atomicOr(a.flag, 1);
+        const bool checked = (ROLE == ROLE_FIRST) ? (chk && j >= a.y0 && j < a.y1) : (vout != NO_STORE);
+        if (checked && !(rho > 0.0 && P > 0.0)) atomicOr(a.flag, 1);
         double coll[NQ];
         collision(a, blocks_of(a), m, rho, vx, vy, P, corr, dxux, dxuy, dyux, dyuy, coll);
 
         const unsigned base = (unsigned)((a.org - 2 + (long)j * a.pitch) * (long)sizeof(T));
         const unsigned pb = (unsigned)(a.plane * (long)sizeof(T));
+        // equilibrium ghost rows and columns keep their (constant) values
+        const bool keep = (ROLE == ROLE_FIRST) &&
+                          (pass || (j < 0 && a.bc[2] == BC_EQUIL) || (j >= a.ny && a.bc[3] == BC_EQUIL));
+        T(*dst)[MW] = (ROLE == ROLE_FIRST) ? ring->v[(j + 4) & (PRING - 1)] : nullptr;
         // planes that do not need row j + 2 DIR first, so its loads have time
 #pragma unroll
-        for (int pass = 0; pass < 2; ++pass) {
+        for (int ps = 0; ps < 2; ++ps) {
 #pragma unroll
             for (int i = 0; i < NQ; ++i) {
-                if ((pass == 1) != (sgy(i) == -DIR)) continue;
-                buf_store(plane_value(i, coll, a), rout, vout, base + (unsigned)i * pb);
+                if ((ps == 1) != (sgy(i) == -DIR)) continue;
+                const T v = plane_value(i, coll, a);
+                if (ROLE == ROLE_FIRST)
+                    dst[i][lane] = keep ? fC[i] : v;
+                else
+                    buf_store(v, rout, vout, base + (unsigned)i * pb);
             }
         }
         velocity(fE, uxE, uyE, a);
     }
 
-    // Output rows [yb, ye), walked from yb up (DIR > 0) or from ye - 1 down.
-    __device__ __forceinline__ void walk(int yb, int ye)
+    // Load the window of output row j: fE = row j - 2 DIR, fB = j - DIR,
+    // fC = j, fD = j + DIR, and the carried face jumps.
+    __device__ __forceinline__ void prime(int j)
     {
-        if (ye <= yb) return;
-        int j = (DIR > 0) ? yb : ye - 1;
         {
             CArgs& a = args();
             load(fE, j - 2 * DIR, a);
@@ -300,21 +406,35 @@ struct Marcher {
             velocity(fD, uxD, uyD, a);
         }
         start_carry();
-        if (MARCH_PF == 2) load(fE, j + 2 * DIR, args());
+        if (PF == 2) load(fE, j + 2 * DIR, args());
+    }
+
+    // Move the window one row on.
+    __device__ __forceinline__ void advance()
+    {
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) {
+            fB[i] = fC[i];
+            fC[i] = fD[i];
+            fD[i] = fE[i];
+            if (PF == 2) fE[i] = fF[i];
+        }
+        uxB = uxC; uyB = uyC;
+        uxC = uxD; uyC = uyD;
+        uxD = uxE; uyD = uyE;
+    }
+
+    // Output rows [yb, ye), walked from yb up (DIR > 0) or from ye - 1 down.
+    __device__ __forceinline__ void walk(int yb, int ye)
+    {
+        if (ye <= yb) return;
+        int j = (DIR > 0) ? yb : ye - 1;
+        prime(j);
         for (int left = ye - yb;;) {
             row(j);
             if (--left == 0) break;
             j += DIR;
-#pragma unroll
-            for (int i = 0; i < NQ; ++i) {
-                fB[i] = fC[i];
-                fC[i] = fD[i];
-                fD[i] = fE[i];
-                if (MARCH_PF == 2) fE[i] = fF[i];
-            }
-            uxB = uxC; uyB = uyC;
-            uxC = uxD; uyC = uyD;
-            uxD = uxE; uyD = uyE;
+            advance();
         }
     }
 };
@@ -354,6 +474,107 @@ __global__ void __launch_bounds__(MW * MWPB, march_min_waves<T>()) k_march(const
         Marcher<LIM, T, 1> mr(&a, fin, fout, bytes, x, out);
         mr.walk(yb, ye);
     }
+}
+
+// Barrier between the two wavefronts of a pair that orders their LDS
+// accesses only: outstanding HBM loads and stores are not waited for.
+__device__ __forceinline__ void pair_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// The walk of a pair through output rows [yb, ye) (H rows) in direction
+// DIR, in H + 6 barrier-separated iterations; r(k) = row of march position
+// k.  The first wavefront makes rows r(-2) .. r(H + 1) of step n + 1 at
+// iterations 0..3 and 5..H+4; the second loads its window r(-2) .. r(1)
+// at iteration 4 and makes row r(k) of step n + 2 at iteration k + 6,
+// reading r(k + 2), which the first finished one iteration before.  A ring
+// slot is rewritten three iterations after it was last read at the
+// earliest (outflow ghost rows read the last interior row).
+template <int LIM, typename T, int DIR>
+__device__ __forceinline__ void pair_walk(int role, CArgs& a, const T* fin, T* fout, unsigned bytes, int x, int lane,
+                                          int yb, int ye, PairRing<T>* ring)
+{
+    const int H = ye - yb, NT = H + 6;
+    const int j0 = (DIR > 0) ? yb : ye - 1;
+    if (role == 0) {
+        Marcher<LIM, T, DIR, ROLE_FIRST> m(&a, fin, fout, bytes, x, lane, ring);
+        int j = j0 - 2 * DIR;
+        m.prime(j);
+        for (int t = 0; t < NT; ++t) {
+            if (t != 4 && t <= H + 4) {
+                m.row(j);
+                j += DIR;
+                m.advance();
+            }
+            pair_sync();
+        }
+    } else {
+        Marcher<LIM, T, DIR, ROLE_SECOND> m(&a, fin, fout, bytes, x, lane, ring);
+        int j = j0;
+        for (int t = 0; t < NT; ++t) {
+            if (t == 4) {
+                m.prime(j);
+            } else if (t >= 6) {
+                m.row(j);
+                j += DIR;
+                m.advance();
+            }
+            pair_sync();
+        }
+    }
+}
+
+// Two steps per pass: block b holds one pair, item (b mod 8) * per_xcd +
+// b / 8 (XCD-aware, as in k_march), numbered band after band, strip by
+// strip within a band; wavefront 0 takes the first step, wavefront 1 the
+// second.  Walls are not supported (their refill sits between two steps).
+#ifndef MARCH2_MINW
+#define MARCH2_MINW 2            // wavefronts per SIMD the pair kernel must fit (register budget)
+#endif
+template <int LIM, typename T>
+__global__ void __launch_bounds__(2 * MW, MARCH2_MINW) k_march2(const T* __restrict__ fin, T* __restrict__ fout,
+                                                          const StepArgs* __restrict__ ap)
+{
+    __shared__ PairRing<T> ring;
+    CArgs& a = *(CArgs*)ap;
+    const int role = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / MW)), lane = threadIdx.x % MW;
+    const int bid = blockIdx.x;
+    const int item = (bid & 7) * a.p_per_xcd + (bid >> 3);
+    if (item >= a.p_nsx * a.p_nby) return;     // both wavefronts
+    const int band = item / a.p_nsx, strip = item - band * a.p_nsx;
+    const int x = a.x0 + strip * POUT - 4 + lane;
+    const int yb = a.y0 + band * a.p_rows, ye = min(yb + a.p_rows, a.y1);
+    const unsigned bytes = (unsigned)(a.elems * (long)sizeof(T));
+    if (MARCH_ALTERNATE && (band & 1))
+        pair_walk<LIM, T, -1>(role, a, fin, fout, bytes, x, lane, yb, ye, &ring);
+    else
+        pair_walk<LIM, T, 1>(role, a, fin, fout, bytes, x, lane, yb, ye, &ring);
+}
+
+// Strips, bands and rows per band of the pair kernel: the launch holds the
+// fraction `frac` of the pairs the device holds at once.
+#ifndef MARCH2_FRAC
+#define MARCH2_FRAC 1.0
+#endif
+// Fewest rows per band for which a handle takes two steps per launch by
+// default (measured: 5-row bands tie with one step per launch, 10-row
+// bands are 10 % faster, 80-row bands 28 %).
+#ifndef MARCH2_MIN_ROWS
+#define MARCH2_MIN_ROWS 8
+#endif
+inline void set_pair(StepArgs& a, long capacity_pairs, double frac)
+{
+    const int ex = a.x1 - a.x0, ey = a.y1 - a.y0;
+    a.p_nsx = (ex + POUT - 1) / POUT;
+    long nby = (long)(frac * (double)capacity_pairs) / (a.p_nsx > 0 ? a.p_nsx : 1);
+    nby = std::max(1L, std::min(nby, (long)ey));
+    a.p_rows = (int)((ey + nby - 1) / nby);
+    if (a.p_rows < 1) a.p_rows = 1;
+    a.p_nby = (ey + a.p_rows - 1) / a.p_rows;
+    a.p_per_xcd = (a.p_nsx * a.p_nby + 7) / 8;
 }
 
 // The march addresses a state buffer with 31-bit byte offsets.

@@ -71,6 +71,8 @@ _lib.mrtfd_footprint.argtypes = [ctypes.POINTER(_Params), ctypes.POINTER(ctypes.
 _lib.mrtfd_init.argtypes = [_H, _vp, _vp, _vp, _vp, ctypes.c_int]
 _lib.mrtfd_step.argtypes = [_H, ctypes.c_long]
 _lib.mrtfd_step_timed.argtypes = [_H, ctypes.c_long, _dp]
+_lib.mrtfd_set_steps_per_launch.argtypes = [_H, ctypes.c_int]
+_lib.mrtfd_get_steps_per_launch.argtypes = [_H, ctypes.POINTER(ctypes.c_int)]
 _lib.mrtfd_macros.argtypes = [_H, _vp, _vp, _vp, _vp, ctypes.c_int]
 _lib.mrtfd_noneq.argtypes = [_H, ctypes.c_int, _vp, ctypes.c_int]
 _lib.mrtfd_get_f.argtypes = [_H, _vp, ctypes.c_int]
@@ -214,6 +216,17 @@ class Solver:
         ms = ctypes.c_double(0.0)
         _check(_lib.mrtfd_step_timed(self._h, int(nsteps), ctypes.byref(ms)))
         return ms.value
+
+    @property
+    def steps_per_launch(self) -> int:
+        """Steps one kernel launch takes: 2 (fused pairs) or 1."""
+        k = ctypes.c_int()
+        _check(_lib.mrtfd_get_steps_per_launch(self._h, ctypes.byref(k)))
+        return k.value
+
+    @steps_per_launch.setter
+    def steps_per_launch(self, k: int):
+        _check(_lib.mrtfd_set_steps_per_launch(self._h, int(k)))
 
     def sync(self):
         _check(_lib.mrtfd_sync(self._h))

@@ -1,0 +1,139 @@
+"""Two steps per launch against one step per launch, on the GPU.
+
+The fused pair kernel takes step n -> n+1 into a ring of rows in LDS and
+step n+1 -> n+2 from there; every node value is formed from the same
+operands in the same order as in the one-step kernel, so the state must
+agree to the last bit after any number of steps (odd counts end with one
+single step).  Cases cover every boundary kind on each axis (periodic
+ghosts computed by translation, equilibrium ghosts passed through, outflow
+ghosts read at their source lane or row), grids narrower than a strip,
+ragged strips, one-row and few-row grids (a band reaching both edges),
+launches with many bands walking in alternate directions, both storage
+precisions and all four limiters.  Walls are rejected for fusion.  The
+fused path is also compared with the oracle directly (every boundary kind,
+both precisions), and the other GPU tests run it wherever it is the default
+(FP64 on large grids, e.g. the full 4096 x 1024 shock-interface windows).
+"""
+import numpy as np
+import pytest
+
+from parity import TOL, assert_parity, f_rel
+from paper_1305_4736_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1305_4736_amd import mrtfd
+    return mrtfd
+
+
+P, O = W.bc("periodic"), W.bc("outflow")
+E1, E2 = W.bc("equilibrium", 1.1, 0.05, -0.02, 0.9), W.bc("equilibrium", 0.8, -0.1, 0.03, 1.2)
+AXES = {"P": (P, P), "E": (E1, E2), "O": (O, O), "EO": (E1, O), "OE": (O, E2)}
+
+
+def state(lib, case, per_launch, nsteps):
+    with lib.Solver(case["params"]) as s:
+        s.steps_per_launch = per_launch
+        assert s.steps_per_launch == per_launch
+        s.init(case["rho"], case["ux"], case["uy"], case["T"])
+        s.step(nsteps)
+        s.sync()
+        return s.get_f(), s.macros()
+
+
+def check(lib, case, nsteps):
+    print(f"[fused] {case['name']} {case['params']['precision']} {case['params']['limiter']} "
+          f"bc={[b['kind'] for b in case['params']['bc']]} n={nsteps}", flush=True)
+    f1, m1 = state(lib, case, 1, nsteps)
+    f2, m2 = state(lib, case, 2, nsteps)
+    assert np.all(np.isfinite(f1))
+    bad = np.argwhere(f1 != f2)
+    assert bad.size == 0, f"{len(bad)} values differ, first (plane, y, x) {bad[:4].tolist()}"
+    for a, b in zip(m1, m2):
+        assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("xa", list(AXES))
+@pytest.mark.parametrize("ya", list(AXES))
+def test_every_boundary_pair(lib, xa, ya):
+    bcs = list(AXES[xa]) + list(AXES[ya])
+    c = W.random_smooth(131, 70, seed=7, bcs=bcs, jumps=True)
+    check(lib, c, 9)
+
+
+@pytest.mark.parametrize("nx,ny", [(1, 1), (3, 2), (5, 1), (7, 9), (56, 5), (57, 6), (60, 3), (113, 1),
+                                   (400, 1), (1, 37), (2, 300)])
+@pytest.mark.parametrize("axes", ["PP", "EO", "OP"])
+def test_small_and_ragged_grids(lib, nx, ny, axes):
+    bcs = list(AXES[axes[0]]) + list(AXES[axes[1]])
+    c = W.random_smooth(nx, ny, seed=nx * 31 + ny, bcs=bcs, jumps=nx > 4)
+    check(lib, c, 8)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("limiter", ["mc", "minmod", "lw", "upwind"])
+def test_precisions_and_limiters(lib, precision, limiter):
+    c = W.random_smooth(300, 97, seed=3, bcs=[E1, O, P, P], limiter=limiter, precision=precision, jumps=True)
+    check(lib, c, 7)
+
+
+def test_many_bands_and_long_run(lib):
+    # 1500 x 700: ~27 strips, ~38 bands of ~18 rows walking in both directions
+    c = W.random_smooth(1500, 700, seed=11, bcs=[E1, O, P, P], jumps=True)
+    check(lib, c, 40)
+
+
+def test_shock_interface_full_size(lib):
+    c = W.shock_interface()
+    check(lib, c, 6)
+
+
+def test_walls_are_not_fused(lib):
+    WL, WH = W.bc("wall", 1.0, 0.0, 0.0, 1.0), W.bc("wall", 1.0, 0.15, 0.0, 1.05)
+    c = W.random_smooth(64, 40, bcs=[P, P, WL, WH])
+    with lib.Solver(c["params"]) as s:
+        assert s.steps_per_launch == 1
+        with pytest.raises(lib.MRTFDError):
+            s.steps_per_launch = 2
+        with pytest.raises(lib.MRTFDError):
+            s.steps_per_launch = 3
+        assert s.steps_per_launch == 1
+    c = W.random_smooth(1024, 512)
+    with lib.Solver(c["params"]) as s:
+        assert s.steps_per_launch == 2          # FP64 on a large grid: fused by default
+        with pytest.raises(lib.MRTFDError):
+            s.steps_per_launch = 0
+    c = W.random_smooth(64, 40)
+    with lib.Solver(c["params"]) as s:
+        assert s.steps_per_launch == 1          # small grid: one step per launch by default
+        s.steps_per_launch = 2
+        assert s.steps_per_launch == 2
+    c = W.random_smooth(1024, 512, precision="fp32")
+    with lib.Solver(c["params"]) as s:
+        assert s.steps_per_launch == 1          # FP32: one step per launch by default
+
+
+@pytest.mark.parametrize("axes", ["PP", "EO", "OE", "EP", "OO"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_fused_against_oracle(lib, orc, axes, precision):
+    bcs = list(AXES[axes[0]]) + list(AXES[axes[1]])
+    c = W.random_smooth(150, 61, seed=5, bcs=bcs, precision=precision, jumps=True)
+    n = 10
+    print(f"[fused-oracle] 150x61 {axes} {precision} n={n}", flush=True)
+    with lib.Solver(c["params"]) as s:
+        s.steps_per_launch = 2
+        s.init(c["rho"], c["ux"], c["uy"], c["T"])
+        s.step(n)
+        s.sync()
+        mg, fg = s.macros(), s.get_f()
+    p = c["params"]
+    fo = orc.run(p, c["rho"], c["ux"], c["uy"], c["T"], n)
+    assert_parity(mg, orc.macros(p, fo), TOL[precision], 1.4, f"fused {axes} {precision}")
+    if precision == "fp64":
+        assert f_rel(fg, fo) <= TOL["fp64"]
