@@ -303,6 +303,24 @@ __device__ __forceinline__ R conv_add(R acc, R l1, R l0, R d1, R nu, R c)
     return fma(-nu, fma(c, l1 - l0, d1), acc);
 }
 
+// A node's new population f + c + a_x + a_y (c the collision increment, a
+// the two convective increments), shared by every step kernel so that all
+// of them round it alike.  FP64 storage seeds the accumulator with c and
+// adds f last; FP32 storage sums its FP32 convection apart and adds f, the
+// sum and c in FP64.
+template <typename T, typename R>
+__device__ __forceinline__ R acc_start(double c)
+{
+    if constexpr (sizeof(T) == 8) return c;
+    else return R(0);
+}
+template <typename T, typename R>
+__device__ __forceinline__ T new_value(R f0, R acc, double c)
+{
+    if constexpr (sizeof(T) == 8) return f0 + acc;
+    else return (T)((double)f0 + (double)acc + c);
+}
+
 template <int LIM, typename R>
 __device__ __forceinline__ R conv1(R acc, R fm2, R fm1, R f0, R fp1, R nu, R c)
 {

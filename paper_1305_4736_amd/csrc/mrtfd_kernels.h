@@ -300,7 +300,7 @@ __device__ __forceinline__ void step_tile(const T* __restrict__ fin, T* __restri
         const T* tb = tile + i * TN;
         const int g = i >> 2;
         const R f0 = tb[c0];
-        R acc = R(0);
+        R acc = acc_start<T, R>(coll[i]);
         if (sgx(i) != 0) {
             const int sx = sgx(i);
             acc = conv1<LIM, R>(acc, tb[c0 - 2 * sx], tb[c0 - sx], f0, tb[c0 + sx], (R)a.nux[g], (R)a.cx[g]);
@@ -309,7 +309,7 @@ __device__ __forceinline__ void step_tile(const T* __restrict__ fin, T* __restri
             const int sy = sgy(i) * TW;
             acc = conv1<LIM, R>(acc, tb[c0 - 2 * sy], tb[c0 - sy], f0, tb[c0 + sy], (R)a.nuy[g], (R)a.cy[g]);
         }
-        fout[(long)i * a.plane + n0] = (T)((double)f0 + (double)acc + coll[i]);
+        fout[(long)i * a.plane + n0] = new_value<T, R>(f0, acc, coll[i]);
     }
 
     int offs[8];

@@ -48,7 +48,7 @@ constexpr int MRMIN = MARCH_RMIN;
 #define MARCH_PF 1               // rows between issuing a row's loads and first using it
 #endif
 #ifndef MARCH2_PF
-#define MARCH2_PF 2              // the same for the first step of a fused pair
+#define MARCH2_PF 1              // the same for the first step of a fused pair (2: no gain measured)
 #endif
 #ifndef MARCH_LOAD_AUX
 #define MARCH_LOAD_AUX 0         // cache policy bits of the state loads
@@ -198,8 +198,7 @@ struct PairRing {
 template <int LIM, typename T, int DIR, int ROLE = ROLE_SINGLE>
 struct Marcher {
     using R = T;   // convection precision (FP64, or FP32 in FP32-storage mode)
-    // prefetch distance: the first step of a pair waits on HBM once per
-    // barrier-bound row, so it loads further ahead; the ring is close
+    // prefetch distance (the second step of a pair reads the ring, which is close)
     static constexpr int PF = (ROLE == ROLE_FIRST) ? MARCH2_PF : (ROLE == ROLE_SECOND) ? 1 : MARCH_PF;
 
     CArgs* argp;                      // kernel arguments
@@ -306,12 +305,13 @@ struct Marcher {
     {
         const int g = i >> 2;
         const R f0 = fC[i];
-        R acc = R(0);
+        R acc = acc_start<T, R>(coll[i]);
         const int sx = sgx(i), sy = sgy(i);
         if (sx != 0) {
-            const R fl = lane_move<FROM_LEFT>(f0), fr = lane_move<FROM_RIGHT>(f0);
-            const R fm1 = (sx > 0) ? fl : fr, fp1 = (sx > 0) ? fr : fl;
-            const R d1 = f0 - fm1, d2 = fp1 - f0;
+            const R fm1 = (sx > 0) ? lane_move<FROM_LEFT>(f0) : lane_move<FROM_RIGHT>(f0);
+            const R d1 = f0 - fm1;
+            // the downstream jump is the next lane's upstream one (same operands)
+            const R d2 = (sx > 0) ? lane_move<FROM_RIGHT>(d1) : lane_move<FROM_LEFT>(d1);
             const R l1 = limited<LIM, R>(d1, d2);
             const R l0 = (sx > 0) ? lane_move<FROM_LEFT>(l1) : lane_move<FROM_RIGHT>(l1);
             acc = conv_add(acc, l1, l0, d1, (R)a.nux[g], (R)a.cx[g]);
@@ -331,7 +331,7 @@ struct Marcher {
             }
             acc = conv_add(acc, l1, l0, d1, (R)a.nuy[g], (R)a.cy[g]);
         }
-        return (T)((double)f0 + (double)acc + coll[i]);
+        return new_value<T, R>(f0, acc, coll[i]);
     }
 
     __device__ __forceinline__ void row(int j)
@@ -497,31 +497,39 @@ template <int LIM, typename T, int DIR>
 __device__ __forceinline__ void pair_walk(int role, CArgs& a, const T* fin, T* fout, unsigned bytes, int x, int lane,
                                           int yb, int ye, PairRing<T>* ring)
 {
-    const int H = ye - yb, NT = H + 6;
+    const int H = ye - yb;
     const int j0 = (DIR > 0) ? yb : ye - 1;
+    // both wavefronts pass H + 6 barriers: 6 in the start-up, one per row
+    // of the steady part
     if (role == 0) {
         Marcher<LIM, T, DIR, ROLE_FIRST> m(&a, fin, fout, bytes, x, lane, ring);
         int j = j0 - 2 * DIR;
         m.prime(j);
-        for (int t = 0; t < NT; ++t) {
-            if (t != 4 && t <= H + 4) {
-                m.row(j);
-                j += DIR;
-                m.advance();
-            }
+        for (int t = 0; t < 4; ++t) {            // rows r(-2) .. r(1)
+            m.row(j);
+            j += DIR;
+            m.advance();
             pair_sync();
         }
+        pair_sync();                             // iteration 4: the second loads its window
+        for (int k = 0; k < H; ++k) {            // iterations 5 .. H + 4: rows r(2) .. r(H + 1)
+            m.row(j);
+            j += DIR;
+            m.advance();
+            pair_sync();
+        }
+        pair_sync();                             // iteration H + 5
     } else {
         Marcher<LIM, T, DIR, ROLE_SECOND> m(&a, fin, fout, bytes, x, lane, ring);
         int j = j0;
-        for (int t = 0; t < NT; ++t) {
-            if (t == 4) {
-                m.prime(j);
-            } else if (t >= 6) {
-                m.row(j);
-                j += DIR;
-                m.advance();
-            }
+        for (int t = 0; t < 4; ++t) pair_sync(); // iterations 0 .. 3
+        m.prime(j);                              // iteration 4
+        pair_sync();
+        pair_sync();                             // iteration 5
+        for (int k = 0; k < H; ++k) {            // iterations 6 .. H + 5: rows r(0) .. r(H - 1)
+            m.row(j);
+            j += DIR;
+            m.advance();
             pair_sync();
         }
     }
