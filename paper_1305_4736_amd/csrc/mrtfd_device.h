@@ -50,6 +50,8 @@ struct StepArgs {
     double b, inv_b, dt;
     double nux[4], nuy[4];      // Courant numbers |v_ia| dt / d_a per group
     double cx[4], cy[4];        // (1 - nu) / 2 per group and axis
+    float nux32[4], nuy32[4];   // the same rounded to FP32 (FP32-storage convection)
+    float cx32[4], cy32[4];
     double c8dt, c9dt;          // -dt (s_8 / s_5 - 1), -dt (s_9 / s_5 - 1); 0 when the correction is off
     double inv2dx, inv2dy;
     double side[4][4];          // (rho, ux, uy, T) of each side: equilibrium ghosts, walls
@@ -319,6 +321,21 @@ __device__ __forceinline__ T new_value(R f0, R acc, double c)
 {
     if constexpr (sizeof(T) == 8) return f0 + acc;
     else return (T)((double)f0 + (double)acc + c);
+}
+
+// Courant number and (1 - nu) / 2 of group g along x (AX = 0) or y (AX = 1)
+// in the convection precision R.
+template <typename R, int AX, class AT>
+__device__ __forceinline__ R nu_of(const AT& a, int g)
+{
+    if constexpr (sizeof(R) == 8) return AX ? a.nuy[g] : a.nux[g];
+    else return AX ? a.nuy32[g] : a.nux32[g];
+}
+template <typename R, int AX, class AT>
+__device__ __forceinline__ R c_of(const AT& a, int g)
+{
+    if constexpr (sizeof(R) == 8) return AX ? a.cy[g] : a.cx[g];
+    else return AX ? a.cy32[g] : a.cx32[g];
 }
 
 template <int LIM, typename R>

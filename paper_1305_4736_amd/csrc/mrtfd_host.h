@@ -134,6 +134,10 @@ inline StepArgs make_args(const mrtfd_params& p, const Layout& L, const Blocks& 
         a.nuy[g] = hb.vmag[g] * p.dt / p.dy;
         a.cx[g] = 0.5 * (1.0 - a.nux[g]);
         a.cy[g] = 0.5 * (1.0 - a.nuy[g]);
+        a.nux32[g] = (float)a.nux[g];
+        a.nuy32[g] = (float)a.nuy[g];
+        a.cx32[g] = (float)a.cx[g];
+        a.cy32[g] = (float)a.cy[g];
     }
     a.correction = p.energy_flux_correction ? 1 : 0;
     a.c8dt = a.correction ? -p.dt * (p.s[7] / p.s[4] - 1.0) : 0.0;

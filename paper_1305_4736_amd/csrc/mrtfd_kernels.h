@@ -303,11 +303,11 @@ __device__ __forceinline__ void step_tile(const T* __restrict__ fin, T* __restri
         R acc = acc_start<T, R>(coll[i]);
         if (sgx(i) != 0) {
             const int sx = sgx(i);
-            acc = conv1<LIM, R>(acc, tb[c0 - 2 * sx], tb[c0 - sx], f0, tb[c0 + sx], (R)a.nux[g], (R)a.cx[g]);
+            acc = conv1<LIM, R>(acc, tb[c0 - 2 * sx], tb[c0 - sx], f0, tb[c0 + sx], nu_of<R, 0>(a, g), c_of<R, 0>(a, g));
         }
         if (!FLAT && sgy(i) != 0) {
             const int sy = sgy(i) * TW;
-            acc = conv1<LIM, R>(acc, tb[c0 - 2 * sy], tb[c0 - sy], f0, tb[c0 + sy], (R)a.nuy[g], (R)a.cy[g]);
+            acc = conv1<LIM, R>(acc, tb[c0 - 2 * sy], tb[c0 - sy], f0, tb[c0 + sy], nu_of<R, 1>(a, g), c_of<R, 1>(a, g));
         }
         fout[(long)i * a.plane + n0] = new_value<T, R>(f0, acc, coll[i]);
     }

@@ -314,7 +314,7 @@ struct Marcher {
             const R d2 = (sx > 0) ? lane_move<FROM_RIGHT>(d1) : lane_move<FROM_LEFT>(d1);
             const R l1 = limited<LIM, R>(d1, d2);
             const R l0 = (sx > 0) ? lane_move<FROM_LEFT>(l1) : lane_move<FROM_RIGHT>(l1);
-            acc = conv_add(acc, l1, l0, d1, (R)a.nux[g], (R)a.cx[g]);
+            acc = conv_add(acc, l1, l0, d1, nu_of<R, 0>(a, g), c_of<R, 0>(a, g));
         }
         if (sy != 0) {
             R d1, l1, l0;
@@ -329,7 +329,7 @@ struct Marcher {
                 l0 = limited<LIM, R>(fD[i] - fE[i], d1);
                 carry[i] = l0;
             }
-            acc = conv_add(acc, l1, l0, d1, (R)a.nuy[g], (R)a.cy[g]);
+            acc = conv_add(acc, l1, l0, d1, nu_of<R, 1>(a, g), c_of<R, 1>(a, g));
         }
         return new_value<T, R>(f0, acc, coll[i]);
     }
