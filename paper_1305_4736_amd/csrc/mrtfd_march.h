@@ -542,6 +542,11 @@ __device__ __forceinline__ void pair_walk(int role, CArgs& a, const T* fin, T* f
 #ifndef MARCH2_MINW
 #define MARCH2_MINW 2            // wavefronts per SIMD the pair kernel must fit (register budget)
 #endif
+// Pairs walk every band in the same direction: 1 % faster than alternating
+// (measured twice), and the CUs run half the code.
+#ifndef MARCH2_ALTERNATE
+#define MARCH2_ALTERNATE 0
+#endif
 template <int LIM, typename T>
 __global__ void __launch_bounds__(2 * MW, MARCH2_MINW) k_march2(const T* __restrict__ fin, T* __restrict__ fout,
                                                           const StepArgs* __restrict__ ap)
@@ -556,7 +561,7 @@ __global__ void __launch_bounds__(2 * MW, MARCH2_MINW) k_march2(const T* __restr
     const int x = a.x0 + strip * POUT - 4 + lane;
     const int yb = a.y0 + band * a.p_rows, ye = min(yb + a.p_rows, a.y1);
     const unsigned bytes = (unsigned)(a.elems * (long)sizeof(T));
-    if (MARCH_ALTERNATE && (band & 1))
+    if (MARCH2_ALTERNATE && (band & 1))
         pair_walk<LIM, T, -1>(role, a, fin, fout, bytes, x, lane, yb, ye, &ring);
     else
         pair_walk<LIM, T, 1>(role, a, fin, fout, bytes, x, lane, yb, ye, &ring);
