@@ -21,6 +21,7 @@ Printed: ONE JSON line with the contract fields plus
   fp64_one_step_per_launch -- the FP64 workload with one step per launch
                   (the default takes two)
   fp32_storage -- the same workload with f stored and convected in FP32
+                  (and fp32_one_step_per_launch)
   limiters_fp64_ms_per_step -- the FP64 step time with each limiter (MC,
                   minmod, Lax-Wendroff, first-order upwind)
   small_configs_fp64_us_per_step -- the latency-bound 400 x 1 Sod tube and
@@ -318,8 +319,14 @@ def main():
         r32 = run_gpu(case32, args.steps, args.warmup, args.noneq_every, log, args.steps_per_launch)
         rl32 = roofline(r32, "fp32")
         extra["fp32_storage"] = {"value": r32["value"], "ms_per_step": r32["ms_per_step"],
+                                 "steps_per_launch": r32["steps_per_launch"],
                                  "roofline_frac": rl32["frac"], "achieved_GBs": rl32["achieved"],
                                  "speedup_vs_fp64": r32["value"] / res["value"]}
+        if not args.steps_per_launch and r32["steps_per_launch"] == 2:
+            r1 = run_gpu(case32, args.steps, args.warmup, args.noneq_every, log, 1)
+            extra["fp32_one_step_per_launch"] = {"value": r1["value"], "ms_per_step": r1["ms_per_step"],
+                                                 "kernel_ms_per_step": round(r1["kernel_ms_avg"], 5),
+                                                 "roofline_frac": roofline(r1, "fp32")["frac"]}
 
     if not args.no_limiters:
         extra["limiters_fp64_ms_per_step"] = run_limiters(log)

@@ -109,10 +109,10 @@ int mrtfd_init(mrtfd_t h, const double* rho, const double* ux, const double* uy,
 
 /* Advance by nsteps explicit stages (Sec. III update eq., every term at
  * level n): a fused kernel computes moments, equilibria, correction,
- * collision, limited fluxes and the update.  With FP64 storage on grids
- * large enough to fill the device (bands of at least 8 rows), where
- * supported (no NEE wall side, state below 2 GiB), one launch takes two
- * steps, the second reading
+ * collision, limited fluxes and the update.  On grids large enough to
+ * fill the device (FP64 from about 1024 x 256 nodes, FP32 storage from
+ * about 2048 x 1024), where supported (no NEE wall side, state below
+ * 2 GiB), one launch takes two steps, the second reading
  * the first's rows from on-chip memory, so the state crosses HBM once per
  * two steps; an odd remainder, and handles set to one step per launch,
  * take one launch per step (the row-marching form for state buffers below
@@ -122,9 +122,9 @@ int mrtfd_init(mrtfd_t h, const double* rho, const double* ux, const double* uy,
  * flagged on the device and reported by mrtfd_sync. */
 int mrtfd_step(mrtfd_t h, long nsteps);
 
-/* Steps taken per kernel launch by mrtfd_step: k = 2 (the default for FP64
- * storage on large grids, where supported) fuses pairs of steps, k = 1
- * (the default otherwise) launches once per step.  Results are bitwise the same either
+/* Steps taken per kernel launch by mrtfd_step: k = 2 (the default on large
+ * grids, where supported) fuses pairs of steps, k = 1 (the default
+ * otherwise) launches once per step.  Results are bitwise the same either
  * way.  MRTFD_EINVAL for k other than 1 or 2,
  * or k = 2 on a handle with a wall side or a state of 2 GiB or more (the
  * setting is then unchanged). */

@@ -273,13 +273,12 @@ int mrtfd_create(const mrtfd_params* p, void* hip_stream, mrtfd_t* out)
         return MRTFD_EDEVICE;
     }
     fill_args(h);
-    // Default: fused pairs for FP64 storage on grids whose pair bands hold
-    // at least MARCH2_MIN_ROWS rows.  A pair's band costs six more barrier
-    // iterations than rows, so short bands (small grids, bound by the
-    // latency of the walk) are faster one step per launch; FP32 storage
-    // gains nothing from fusing (its step is bound by its FP64 collision
-    // arithmetic, which fusing does not reduce).
-    h->per_launch = (pair_supported(h) && h->p.precision == MRTFD_FP64 && h->args.p_rows >= MARCH2_MIN_ROWS) ? 2 : 1;
+    // Default: fused pairs on grids whose pair bands are tall enough.  A
+    // pair's band costs six more barrier iterations than rows, so short
+    // bands (small grids, bound by the latency of the walk) are faster one
+    // step per launch.
+    const int min_rows = (h->p.precision == MRTFD_FP32_STORAGE) ? MARCH2_MIN_ROWS32 : MARCH2_MIN_ROWS64;
+    h->per_launch = (pair_supported(h) && h->args.p_rows >= min_rows) ? 2 : 1;
     if (hipMemcpyAsync(h->blocks_dev, &h->blocks, sizeof(Blocks), hipMemcpyHostToDevice, h->stream) != hipSuccess ||
         hipMemcpyAsync(h->args_dev, &h->args, sizeof(StepArgs), hipMemcpyHostToDevice, h->stream) != hipSuccess) {
         mrtfd_destroy(h);

@@ -59,6 +59,14 @@ constexpr int MRMIN = MARCH_RMIN;
 #ifndef MARCH_ALTERNATE
 #define MARCH_ALTERNATE 1        // adjacent bands march in opposite directions
 #endif
+// Wave priority (s_setprio) of the first wavefront of a fused pair: with the
+// first step ahead in the SIMDs' issue order the pair kernel runs 6.5 %
+// faster (FP64; FP32 7 %); priority 3 measured the same, raising the second
+// wavefront's or raising it only while a row's loads are issued gained
+// nothing, nor did the latter for the one-step kernel.
+#ifndef MARCH2_PRIO_FIRST
+#define MARCH2_PRIO_FIRST 1
+#endif
 // Bands are sized so that the launch has this fraction of the wavefronts
 // the device holds at once.  FP64 does best with about one wavefront per
 // SIMD (longer bands: fewer halo rows and fewer concurrent streams); FP32,
@@ -502,6 +510,9 @@ __device__ __forceinline__ void pair_walk(int role, CArgs& a, const T* fin, T* f
     // both wavefronts pass H + 6 barriers: 6 in the start-up, one per row
     // of the steady part
     if (role == 0) {
+#if MARCH2_PRIO_FIRST
+        __builtin_amdgcn_s_setprio(MARCH2_PRIO_FIRST);
+#endif
         Marcher<LIM, T, DIR, ROLE_FIRST> m(&a, fin, fout, bytes, x, lane, ring);
         int j = j0 - 2 * DIR;
         m.prime(j);
@@ -572,11 +583,15 @@ __global__ void __launch_bounds__(2 * MW, MARCH2_MINW) k_march2(const T* __restr
 #ifndef MARCH2_FRAC
 #define MARCH2_FRAC 1.0
 #endif
-// Fewest rows per band for which a handle takes two steps per launch by
-// default (measured: 5-row bands tie with one step per launch, 10-row
-// bands are 10 % faster, 80-row bands 28 %).
-#ifndef MARCH2_MIN_ROWS
-#define MARCH2_MIN_ROWS 8
+// Fewest rows per pair band for which a handle takes two steps per launch
+// by default.  Measured: FP64 2-row bands are 10 % slower fused, 5-row
+// bands 9 % faster, 80-row bands 26 %; FP32 19-row bands tie, 38-row bands
+// are 7 % faster, 80-row bands 6 %.
+#ifndef MARCH2_MIN_ROWS64
+#define MARCH2_MIN_ROWS64 4
+#endif
+#ifndef MARCH2_MIN_ROWS32
+#define MARCH2_MIN_ROWS32 32
 #endif
 inline void set_pair(StepArgs& a, long capacity_pairs, double frac)
 {

@@ -115,7 +115,10 @@ def test_walls_are_not_fused(lib):
         assert s.steps_per_launch == 2
     c = W.random_smooth(1024, 512, precision="fp32")
     with lib.Solver(c["params"]) as s:
-        assert s.steps_per_launch == 1          # FP32: one step per launch by default
+        assert s.steps_per_launch == 1          # FP32 fuses only on larger grids
+    c = W.random_smooth(4096, 1024, precision="fp32")
+    with lib.Solver(c["params"]) as s:
+        assert s.steps_per_launch == 2
 
 
 @pytest.mark.parametrize("axes", ["PP", "EO", "OE", "EP", "OO"])
