@@ -1,16 +1,19 @@
 // mrtfd.hip -- C ABI (include/mrtfd.h) of the D2V16 MRT finite-difference
 // lattice-Boltzmann step (arXiv:1305.4736): single-instance entry points.
 //
-// One time step is ONE launch of the fused step kernel (the row-marching
-// form of mrtfd_march.h): each node's new populations come, from level n
-// only, from its moments
+// A time step is one pass of a fused step kernel (mrtfd_march.h: the
+// row-marching form, one step per launch or, on large grids without walls,
+// two steps per launch through an LDS ring of rows): each node's new
+// populations come, from level n only, from its moments
 // and macroscopic state (Sec. II), the velocity of its four axis neighbours
 // (energy-flux correction, Sec. II), the equilibria (Appendix), the relaxed
 // residual mapped back to velocity space (Sec. III update eq.), the limited x
 // and y flux differences of its 16 populations (Sec. III flux and limiter
-// eqs.), the new populations and the periodic / outflow ghost images it
-// owns.  Walls, if any, are refilled by a small kernel after the step;
-// equilibrium ghosts are constant and written once.
+// eqs.) and the new populations.  The march reads periodic and outflow
+// sides at their source nodes (the LDS-tile form for states of 2 GiB and
+// more writes those ghost images instead); walls, if any, are refilled by
+// a small kernel after the step; equilibrium ghosts are constant and
+// written once.
 #include <hip/hip_runtime.h>
 
 #include <new>

@@ -139,3 +139,22 @@ def test_fused_against_oracle(lib, orc, axes, precision):
     assert_parity(mg, orc.macros(p, fo), TOL[precision], 1.4, f"fused {axes} {precision}")
     if precision == "fp64":
         assert f_rel(fg, fo) <= TOL["fp64"]
+
+
+@pytest.mark.parametrize("node", [(0, 0), (4, 55), (17, 56), (40, 111), (69, 149)])
+@pytest.mark.parametrize("nsteps", [1, 2, 5])
+def test_nonfinite_is_reported_fused(lib, node, nsteps):
+    # nodes at the grid's corners and on strip edges (56-column strips)
+    c = W.random_smooth(150, 70, seed=4, bcs=[E1, O, P, P])
+    with lib.Solver(c["params"]) as s:
+        s.steps_per_launch = 2
+        s.init(c["rho"], c["ux"], c["uy"], c["T"])
+        s.step(2)
+        s.sync()
+        f = s.get_f()
+        f[:, node[0], node[1]] = np.nan
+        s.set_f(f)
+        s.step(nsteps)
+        with pytest.raises(lib.NonFiniteError):
+            s.sync()
+        s.sync()    # the flag was cleared
