@@ -111,7 +111,7 @@ int mrtfd_init(mrtfd_t h, const double* rho, const double* ux, const double* uy,
  * level n): a fused kernel computes moments, equilibria, correction,
  * collision, limited fluxes and the update.  On grids large enough to
  * fill the device (FP64 from about 1024 x 256 nodes, FP32 storage from
- * about 2048 x 1024), where supported (no NEE wall side, state below
+ * about 1024 x 512), where supported (no NEE wall side, state below
  * 2 GiB), one launch takes two steps, the second reading
  * the first's rows from on-chip memory, so the state crosses HBM once per
  * two steps; an odd remainder, and handles set to one step per launch,

@@ -44,12 +44,6 @@ constexpr int MWPB = MARCH_WPB;  // wavefronts (independent strips) per block
 #define MARCH_RMIN 1
 #endif
 constexpr int MRMIN = MARCH_RMIN;
-#ifndef MARCH_PF
-#define MARCH_PF 1               // rows between issuing a row's loads and first using it
-#endif
-#ifndef MARCH2_PF
-#define MARCH2_PF 1              // the same for the first step of a fused pair (2: no gain measured)
-#endif
 #ifndef MARCH_LOAD_AUX
 #define MARCH_LOAD_AUX 0         // cache policy bits of the state loads
 #endif
@@ -195,10 +189,12 @@ struct PairRing {
 };
 
 // One wavefront's walk through its band in direction DIR (+1: increasing y).
-// fB, fC, fD hold rows j - DIR, j, j + DIR of output row j and fE row
-// j + 2 DIR.  With PF = 1 the loads of row j + 2 DIR are issued at the
-// start of row j; with PF = 2 they were issued one row earlier and fF
-// receives row j + 3 DIR while row j is computed.
+// The window W holds four rows of all 16 planes: for output row j walked in
+// phase PH, slot PH & 3 holds row j - DIR, (PH + 1) & 3 row j, (PH + 2) & 3
+// row j + DIR, and (PH + 3) & 3 receives row j + 2 DIR, whose loads are
+// issued at the start of row j.  The next row is walked in phase PH + 1, so four
+// rows in phases 0..3 move the window by renaming alone; advance() moves it
+// by copies and keeps phase 0.
 //
 // In a fused pair (ROLE_FIRST / ROLE_SECOND) the lanes of both wavefronts
 // are columns x0 + 56 s - 4 .. x0 + 56 s + 59 of strip s.  The first step
@@ -206,8 +202,8 @@ struct PairRing {
 template <int LIM, typename T, int DIR, int ROLE = ROLE_SINGLE>
 struct Marcher {
     using R = T;   // convection precision (FP64, or FP32 in FP32-storage mode)
-    // prefetch distance (the second step of a pair reads the ring, which is close)
-    static constexpr int PF = (ROLE == ROLE_FIRST) ? MARCH2_PF : (ROLE == ROLE_SECOND) ? 1 : MARCH_PF;
+    using value_type = T;
+    static constexpr int dir = DIR;
 
     CArgs* argp;                      // kernel arguments
     __amdgpu_buffer_rsrc_t rin, rout;
@@ -217,8 +213,8 @@ struct Marcher {
     int lane;                         // ROLE_FIRST: own lane; ROLE_SECOND: lane read from the ring
     bool pass;                        // ROLE_FIRST: an equilibrium ghost column (value passes through)
     bool chk;                         // ROLE_FIRST: an interior column this wavefront checks
-    T fB[NQ], fC[NQ], fD[NQ], fE[NQ], fF[NQ];
-    double uxB, uyB, uxC, uyC, uxD, uyD, uxE, uyE;
+    T W[4][NQ];                       // the window (see above)
+    double U[4], V[4];                // velocity (u_x, u_y) of each window row
     R carry[NQ];                      // limited jump of the y face carried from the previous row
 
     __device__ __forceinline__ Marcher(CArgs* ap, const T* fin, T* fout, unsigned bytes, int x, bool out)
@@ -294,10 +290,14 @@ struct Marcher {
     }
 
     // Limited jump of the y face carried into the first output row j0 (the
-    // value the row before j0 would have left): fE = row j0 - 2 DIR,
-    // fB = j0 - DIR, fC = j0, fD = j0 + DIR.
+    // value the row before j0 would have left), in phase 0: W[3] = row
+    // j0 - 2 DIR, W[0] = j0 - DIR, W[1] = j0, W[2] = j0 + DIR.
     __device__ __forceinline__ void start_carry()
     {
+        const T(&fB)[NQ] = W[0];
+        const T(&fC)[NQ] = W[1];
+        const T(&fD)[NQ] = W[2];
+        const T(&fE)[NQ] = W[3];
 #pragma unroll
         for (int i = 0; i < NQ; ++i) {
             const int sy = sgy(i);
@@ -308,9 +308,14 @@ struct Marcher {
         }
     }
 
-    // New value of plane i at output row j.
+    // New value of plane i at output row j, walked in phase PH.
+    template <int PH>
     __device__ __forceinline__ T plane_value(int i, const double* coll, CArgs& a)
     {
+        const T(&fB)[NQ] = W[PH & 3];
+        const T(&fC)[NQ] = W[(PH + 1) & 3];
+        const T(&fD)[NQ] = W[(PH + 2) & 3];
+        const T(&fE)[NQ] = W[(PH + 3) & 3];
         const int g = i >> 2;
         const R f0 = fC[i];
         R acc = acc_start<T, R>(coll[i]);
@@ -342,33 +347,33 @@ struct Marcher {
         return new_value<T, R>(f0, acc, coll[i]);
     }
 
+    // Output row j in phase PH.
+    template <int PH>
     __device__ __forceinline__ void row(int j)
     {
+        constexpr int B = PH & 3, C = (PH + 1) & 3, D = (PH + 2) & 3, E = (PH + 3) & 3;
         CArgs& a = args();
-        if (PF == 1)
-            load(fE, j + 2 * DIR, a);
-        else
-            load(fF, j + 3 * DIR, a);
+        load(W[E], j + 2 * DIR, a);
 
         // moments, equilibria, correction and collision of row j
         double m[NQ];
         {
             double g[NQ];
 #pragma unroll
-            for (int i = 0; i < NQ; ++i) g[i] = (double)fC[i];
+            for (int i = 0; i < NQ; ++i) g[i] = (double)W[C][i];
             Sums sm = all_sums(g);
             moments(blocks_of(a), sm, m);
         }
         const double rho = m[0];
-        const double vx = uxC, vy = uyC;
+        const double vx = U[C], vy = V[C];
         const double P = (m[3] - rho * (vx * vx + vy * vy)) * a.inv_b;
         const bool corr = a.correction != 0;
         double dxux = 0.0, dxuy = 0.0, dyux = 0.0, dyuy = 0.0;
         if (corr) {
             dxux = (lane_move<FROM_RIGHT>(vx) - lane_move<FROM_LEFT>(vx)) * a.inv2dx;
             dxuy = (lane_move<FROM_RIGHT>(vy) - lane_move<FROM_LEFT>(vy)) * a.inv2dx;
-            const double uxp = (DIR > 0) ? uxD : uxB, uxm = (DIR > 0) ? uxB : uxD;
-            const double uyp = (DIR > 0) ? uyD : uyB, uym = (DIR > 0) ? uyB : uyD;
+            const double uxp = (DIR > 0) ? U[D] : U[B], uxm = (DIR > 0) ? U[B] : U[D];
+            const double uyp = (DIR > 0) ? V[D] : V[B], uym = (DIR > 0) ? V[B] : V[D];
             dyux = (uxp - uxm) * a.inv2dy;
             dyuy = (uyp - uym) * a.inv2dy;
         }
@@ -389,47 +394,45 @@ struct Marcher {
 #pragma unroll
             for (int i = 0; i < NQ; ++i) {
                 if ((ps == 1) != (sgy(i) == -DIR)) continue;
-                const T v = plane_value(i, coll, a);
+                const T v = plane_value<PH>(i, coll, a);
                 if (ROLE == ROLE_FIRST)
-                    dst[i][lane] = keep ? fC[i] : v;
+                    dst[i][lane] = keep ? W[C][i] : v;
                 else
                     buf_store(v, rout, vout, base + (unsigned)i * pb);
             }
         }
-        velocity(fE, uxE, uyE, a);
+        velocity(W[E], U[E], V[E], a);
     }
 
-    // Load the window of output row j: fE = row j - 2 DIR, fB = j - DIR,
-    // fC = j, fD = j + DIR, and the carried face jumps.
+    // Load the window of output row j in phase 0 (W[3] = row j - 2 DIR,
+    // W[0] = j - DIR, W[1] = j, W[2] = j + DIR) and the carried face jumps.
     __device__ __forceinline__ void prime(int j)
     {
         {
             CArgs& a = args();
-            load(fE, j - 2 * DIR, a);
-            load(fB, j - DIR, a);
-            load(fC, j, a);
-            load(fD, j + DIR, a);
-            velocity(fB, uxB, uyB, a);
-            velocity(fC, uxC, uyC, a);
-            velocity(fD, uxD, uyD, a);
+            load(W[3], j - 2 * DIR, a);
+            load(W[0], j - DIR, a);
+            load(W[1], j, a);
+            load(W[2], j + DIR, a);
+            velocity(W[0], U[0], V[0], a);
+            velocity(W[1], U[1], V[1], a);
+            velocity(W[2], U[2], V[2], a);
         }
         start_carry();
-        if (PF == 2) load(fE, j + 2 * DIR, args());
     }
 
-    // Move the window one row on.
+    // Move the window one row on by copies (phase 0 before and after).
     __device__ __forceinline__ void advance()
     {
 #pragma unroll
         for (int i = 0; i < NQ; ++i) {
-            fB[i] = fC[i];
-            fC[i] = fD[i];
-            fD[i] = fE[i];
-            if (PF == 2) fE[i] = fF[i];
+            W[0][i] = W[1][i];
+            W[1][i] = W[2][i];
+            W[2][i] = W[3][i];
         }
-        uxB = uxC; uyB = uyC;
-        uxC = uxD; uyC = uyD;
-        uxD = uxE; uyD = uyE;
+        U[0] = U[1]; V[0] = V[1];
+        U[1] = U[2]; V[1] = V[2];
+        U[2] = U[3]; V[2] = V[3];
     }
 
     // Output rows [yb, ye), walked from yb up (DIR > 0) or from ye - 1 down.
@@ -439,7 +442,7 @@ struct Marcher {
         int j = (DIR > 0) ? yb : ye - 1;
         prime(j);
         for (int left = ye - yb;;) {
-            row(j);
+            row<0>(j);
             if (--left == 0) break;
             j += DIR;
             advance();
@@ -484,6 +487,18 @@ __global__ void __launch_bounds__(MW * MWPB, march_min_waves<T>()) k_march(const
     }
 }
 
+// Steady rows of a pair four at a time with the window moved by renaming:
+// FP32 storage 7 % faster (110.4 against 118.9 us per step at 4096 x 1024;
+// the compiler uses the register room it gains to load further ahead), FP64
+// 6 % slower (its registers run out: 256 with spills, and the kernel's code
+// outgrows the instruction cache).
+#ifndef MARCH2_RENAME64
+#define MARCH2_RENAME64 0
+#endif
+#ifndef MARCH2_RENAME32
+#define MARCH2_RENAME32 1
+#endif
+
 // Barrier between the two wavefronts of a pair that orders their LDS
 // accesses only: outstanding HBM loads and stores are not waited for.
 __device__ __forceinline__ void pair_sync()
@@ -491,6 +506,36 @@ __device__ __forceinline__ void pair_sync()
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
     __builtin_amdgcn_s_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// n rows of a pair's steady part from row j on, one barrier after each:
+// four rows per trip in phases 0..3 (the window moves by renaming) where
+// that is faster, the rest in phase 0 with copies.
+template <class M>
+__device__ __forceinline__ void pair_rows(M& m, int j, int n)
+{
+    constexpr int DIR = M::dir;
+    constexpr bool rename = (sizeof(typename M::value_type) == 8) ? MARCH2_RENAME64 : MARCH2_RENAME32;
+    int k = 0;
+    if (rename) {
+        for (; k + 4 <= n; k += 4) {
+            m.template row<0>(j);
+            pair_sync();
+            m.template row<1>(j + DIR);
+            pair_sync();
+            m.template row<2>(j + 2 * DIR);
+            pair_sync();
+            m.template row<3>(j + 3 * DIR);
+            pair_sync();
+            j += 4 * DIR;
+        }
+    }
+    for (; k < n; ++k) {
+        m.template row<0>(j);
+        j += DIR;
+        m.advance();
+        pair_sync();
+    }
 }
 
 // The walk of a pair through output rows [yb, ye) (H rows) in direction
@@ -517,18 +562,13 @@ __device__ __forceinline__ void pair_walk(int role, CArgs& a, const T* fin, T* f
         int j = j0 - 2 * DIR;
         m.prime(j);
         for (int t = 0; t < 4; ++t) {            // rows r(-2) .. r(1)
-            m.row(j);
+            m.template row<0>(j);
             j += DIR;
             m.advance();
             pair_sync();
         }
         pair_sync();                             // iteration 4: the second loads its window
-        for (int k = 0; k < H; ++k) {            // iterations 5 .. H + 4: rows r(2) .. r(H + 1)
-            m.row(j);
-            j += DIR;
-            m.advance();
-            pair_sync();
-        }
+        pair_rows(m, j, H);                      // iterations 5 .. H + 4: rows r(2) .. r(H + 1)
         pair_sync();                             // iteration H + 5
     } else {
         Marcher<LIM, T, DIR, ROLE_SECOND> m(&a, fin, fout, bytes, x, lane, ring);
@@ -537,12 +577,7 @@ __device__ __forceinline__ void pair_walk(int role, CArgs& a, const T* fin, T* f
         m.prime(j);                              // iteration 4
         pair_sync();
         pair_sync();                             // iteration 5
-        for (int k = 0; k < H; ++k) {            // iterations 6 .. H + 5: rows r(0) .. r(H - 1)
-            m.row(j);
-            j += DIR;
-            m.advance();
-            pair_sync();
-        }
+        pair_rows(m, j, H);                      // iterations 6 .. H + 5: rows r(0) .. r(H - 1)
     }
 }
 
@@ -585,13 +620,13 @@ __global__ void __launch_bounds__(2 * MW, MARCH2_MINW) k_march2(const T* __restr
 #endif
 // Fewest rows per pair band for which a handle takes two steps per launch
 // by default.  Measured: FP64 2-row bands are 10 % slower fused, 5-row
-// bands 9 % faster, 80-row bands 26 %; FP32 19-row bands tie, 38-row bands
-// are 7 % faster, 80-row bands 6 %.
+// bands 9 % faster, 80-row bands 28 %; FP32 5-row bands 2 % slower,
+// 10-row bands 1 % faster, 19-row bands 4 %, 80-row bands 12 %.
 #ifndef MARCH2_MIN_ROWS64
 #define MARCH2_MIN_ROWS64 4
 #endif
 #ifndef MARCH2_MIN_ROWS32
-#define MARCH2_MIN_ROWS32 32
+#define MARCH2_MIN_ROWS32 8
 #endif
 inline void set_pair(StepArgs& a, long capacity_pairs, double frac)
 {
