@@ -145,7 +145,7 @@ def roofline(res, precision):
     return out
 
 
-def cpu_baseline(log, nsteps=2):
+def cpu_baseline(log, nsteps=6):
     """The FP64 oracle (serial C) on `nsteps` steps of the full grid."""
     import oracle
     from paper_1305_4736_amd import workloads as W
