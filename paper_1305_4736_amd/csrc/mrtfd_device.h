@@ -12,6 +12,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 namespace mrtfd {
 
 constexpr int NQ = 16;
@@ -304,6 +306,15 @@ __device__ __forceinline__ R conv_add(R acc, R l1, R l0, R d1, R nu, R c)
 {
     return fma(-nu, fma(c, l1 - l0, d1), acc);
 }
+
+// Precision of the convective part of the step for a storage type: FP64
+// storage convects in FP64; FP32 storage convects in FP32 (MRTFD_CONV64 = 1
+// makes it FP64, with FP32 values widened before any difference is taken).
+#ifndef MRTFD_CONV64
+#define MRTFD_CONV64 0
+#endif
+template <typename T>
+using conv_t = typename std::conditional<(MRTFD_CONV64 != 0), double, T>::type;
 
 // A node's new population f + c + a_x + a_y (c the collision increment, a
 // the two convective increments), shared by every step kernel so that all

@@ -294,7 +294,7 @@ __device__ __forceinline__ void step_tile(const T* __restrict__ fin, T* __restri
     collision(a, *a.Bp, m, rho, ux, uy, P, corr, dxux, dxuy, dyux, dyuy, coll);
 
     // ---- limited fluxes and the update, plane by plane
-    using R = T;   // convection precision (FP64, or FP32 in FP32-storage mode)
+    using R = conv_t<T>;   // convection precision
 #pragma unroll
     for (int i = 0; i < NQ; ++i) {
         const T* tb = tile + i * TN;

@@ -201,7 +201,7 @@ struct PairRing {
 // is valid on lanes 2..61, the second on lanes 4..59 (its output).
 template <int LIM, typename T, int DIR, int ROLE = ROLE_SINGLE>
 struct Marcher {
-    using R = T;   // convection precision (FP64, or FP32 in FP32-storage mode)
+    using R = conv_t<T>;   // convection precision
     using value_type = T;
     static constexpr int dir = DIR;
 
@@ -302,9 +302,9 @@ struct Marcher {
         for (int i = 0; i < NQ; ++i) {
             const int sy = sgy(i);
             if (sy == DIR)
-                carry[i] = limited<LIM, R>(fB[i] - fE[i], fC[i] - fB[i]);
+                carry[i] = limited<LIM, R>((R)fB[i] - (R)fE[i], (R)fC[i] - (R)fB[i]);
             else if (sy == -DIR)
-                carry[i] = limited<LIM, R>(fC[i] - fD[i], fB[i] - fC[i]);
+                carry[i] = limited<LIM, R>((R)fC[i] - (R)fD[i], (R)fB[i] - (R)fC[i]);
         }
     }
 
@@ -332,14 +332,14 @@ struct Marcher {
         if (sy != 0) {
             R d1, l1, l0;
             if (sy == DIR) {        // upstream row is behind: its face value is carried
-                d1 = f0 - fB[i];
-                l1 = limited<LIM, R>(d1, fD[i] - f0);
+                d1 = f0 - (R)fB[i];
+                l1 = limited<LIM, R>(d1, (R)fD[i] - f0);
                 l0 = carry[i];
                 carry[i] = l1;
             } else {                // upstream row is ahead: needs row j + 2 DIR
-                d1 = f0 - fD[i];
+                d1 = f0 - (R)fD[i];
                 l1 = carry[i];
-                l0 = limited<LIM, R>(fD[i] - fE[i], d1);
+                l0 = limited<LIM, R>((R)fD[i] - (R)fE[i], d1);
                 carry[i] = l0;
             }
             acc = conv_add(acc, l1, l0, d1, nu_of<R, 1>(a, g), c_of<R, 1>(a, g));
