@@ -13,6 +13,10 @@
 // Shape classes: the row-marching strips of mrtfd_march.h (60 output
 // columns x bands of up to 12 rows per wavefront), and LDS tiles of 256
 // threads: 32 x 8, 64 x 4, 128 x 2, and 256 x 1 rows for one-row instances.
+// Strip slots without walls and with at least 8 rows take two steps per
+// launch (k_march2_batch, bands of up to 32 rows) in two-step rounds, which
+// the batch runs while every such slot has two steps left; the other slots
+// then take two one-step launches.
 // Each slot gets the class with the smallest estimated cost (work units x
 // cost per unit; a unit is a tile, or one row of a strip including the halo
 // rows of its bands); mrtfd_batch_autotune measures the cost per unit of
@@ -33,6 +37,9 @@ namespace {
 
 constexpr int NSHAPE = 5;
 constexpr int MARCH = 4;   // index of the row-marching class
+// work lists: one per class, then the strip slots split into those that
+// take two steps per launch in two-step rounds and the others
+constexpr int LIST_PAIR = NSHAPE, LIST_SINGLE = NSHAPE + 1, NLIST = NSHAPE + 2;
 struct ShapeDef {
     int txw, byr;
     bool flat;
@@ -67,10 +74,11 @@ long tiles_of(const mrtfd_params& p, int s)
     return (long)((ex + SHAPES[s].txw - 1) / SHAPES[s].txw) * ((ey + SHAPES[s].byr - 1) / SHAPES[s].byr);
 }
 
-// Work items of one launch for a slot in class s.
+// Work items of one launch for a slot in work list s.
 long items_of(const StepArgs& a, int s)
 {
-    return (s == MARCH) ? (long)a.m_nsx * a.m_nby : (long)a.ntx * a.nty;
+    if (s == LIST_PAIR) return (long)a.p_nsx * a.p_nby;
+    return (s == MARCH || s == LIST_SINGLE) ? (long)a.m_nsx * a.m_nby : (long)a.ntx * a.nty;
 }
 
 }  // namespace
@@ -86,10 +94,13 @@ struct mrtfd_batch_s {
     BatchSlot* d_slot;
     Blocks* d_blocks;
     int* d_flags;
-    int* d_lists;                       // NSHAPE x (capacity + 1) prefixes, then NSHAPE x capacity slot lists, then walls
-    int nlist[NSHAPE], nwall;
+    int* d_lists;                       // NLIST x (capacity + 1) prefixes, then NLIST x capacity slot lists, then walls
+    int nlist[NLIST], nwall;
     bool dirty;
-    long L;
+    long L;                             // steps taken by the batch
+    long R;                             // rounds (one or two steps each)
+    std::vector<long> rstop;            // R at which a pair slot stopped stepping (LONG_MAX while it steps)
+    int per_launch;                     // 2: two-step rounds where possible; 1: one step per round
     double cost[NSHAPE];                // device microseconds per work unit of each class
     double launch_us[NSHAPE];           // device microseconds of one launch of a class, beside its work
     double* staging;
@@ -97,13 +108,15 @@ struct mrtfd_batch_s {
     hipEvent_t ev0, ev1;
     int max_blocks;
     int march_blocks;                   // resident blocks of the strip kernel on the device
+    int pair_blocks;                    // resident blocks (pairs) of the two-step strip kernel
+    long pair_items;                    // work items (pair bands x strips) of the two-step list
 };
 
 namespace {
 
 int* prefix_dev(mrtfd_batch_s* B, int s) { return B->d_lists + s * (B->capacity + 1); }
-int* list_dev(mrtfd_batch_s* B, int s) { return B->d_lists + NSHAPE * (B->capacity + 1) + s * B->capacity; }
-int* wall_dev(mrtfd_batch_s* B) { return B->d_lists + NSHAPE * (B->capacity + 1) + NSHAPE * B->capacity; }
+int* list_dev(mrtfd_batch_s* B, int s) { return B->d_lists + NLIST * (B->capacity + 1) + s * B->capacity; }
+int* wall_dev(mrtfd_batch_s* B) { return B->d_lists + NLIST * (B->capacity + 1) + NLIST * B->capacity; }
 
 int check_slot(mrtfd_batch_s* B, int k)
 {
@@ -137,12 +150,44 @@ int pick_shape(const mrtfd_batch_s* B, const mrtfd_params& p)
     return best;
 }
 
+// Whether slot k takes two steps per launch in two-step rounds: a strip
+// slot without walls and with at least MARCH2_BATCH_MIN_ROWS rows.
+bool pair_capable(const mrtfd_batch_s* B, int k)
+{
+    if (B->per_launch != 2 || B->shape[k] != MARCH) return false;
+    const mrtfd_params& p = B->prm[k];
+    for (int q = 0; q < 4; ++q)
+        if (p.bc[q].kind == BC_WALL) return false;
+    return p.ny >= MARCH2_BATCH_MIN_ROWS;
+}
+
+// Buffer holding the slot's current state: the parity of its clock (R for
+// pair slots, frozen where they stopped; L for the others, frozen at stop).
+int current_buffer(const mrtfd_batch_s* B, int k)
+{
+    const BatchSlot& sl = B->slot[k];
+    const long c = sl.pair ? std::min(B->R, B->rstop[k]) : std::min(B->L, sl.stop);
+    return (int)(((c - sl.pstart) % 2 + 2) % 2);
+}
+
+// Restart slot k's clock so that buffer `cur` is current under its rule.
+void rebase(mrtfd_batch_s* B, int k, int cur)
+{
+    BatchSlot& sl = B->slot[k];
+    B->rstop[k] = (B->L >= sl.stop) ? B->R : LONG_MAX;
+    const long c = sl.pair ? B->R : std::min(B->L, sl.stop);
+    sl.pstart = c - cur;
+}
+
+// Arguments and pair flag of slot k for its class (the caller rebases).
 void set_args(mrtfd_batch_s* B, int k)
 {
     const int s = B->shape[k];
     const ShapeDef& sd = SHAPES[s == MARCH ? 0 : s];
     B->slot[k].a = make_args(B->prm[k], B->lay[k], B->blk[k], B->d_blocks + k, B->d_flags + k, sd.txw, sd.byr, 1 << 20);
     set_march_rows(B->slot[k].a, MBROWS);
+    set_pair_rows(B->slot[k].a, MBROWS2);
+    B->slot[k].pair = pair_capable(B, k) ? 1 : 0;
 }
 
 int upload_slot(mrtfd_batch_s* B, int k)
@@ -151,17 +196,21 @@ int upload_slot(mrtfd_batch_s* B, int k)
     return MRTFD_OK;
 }
 
-// Rebuild the per-shape work lists over slots that still step.
+// Rebuild the work lists over slots that still step.
 int rebuild_lists(mrtfd_batch_s* B)
 {
-    std::vector<int> host(NSHAPE * (B->capacity + 1) + NSHAPE * B->capacity + B->capacity, 0);
+    std::vector<int> host(NLIST * (B->capacity + 1) + NLIST * B->capacity + B->capacity, 0);
     B->nwall = 0;
-    for (int s = 0; s < NSHAPE; ++s) {
+    for (int s = 0; s < NLIST; ++s) {
         int n = 0, acc = 0;
         int* pre = host.data() + s * (B->capacity + 1);
-        int* lst = host.data() + NSHAPE * (B->capacity + 1) + s * B->capacity;
+        int* lst = host.data() + NLIST * (B->capacity + 1) + s * B->capacity;
         for (int k = 0; k < B->capacity; ++k) {
-            if (!B->used[k] || B->shape[k] != s || B->L >= B->slot[k].stop) continue;
+            if (!B->used[k] || B->L >= B->slot[k].stop) continue;
+            const int cls = (s == LIST_PAIR || s == LIST_SINGLE) ? MARCH : s;
+            if (B->shape[k] != cls) continue;
+            if (s == LIST_PAIR && !B->slot[k].pair) continue;
+            if (s == LIST_SINGLE && B->slot[k].pair) continue;
             pre[n] = acc;
             lst[n] = k;
             acc += (int)items_of(B->slot[k].a, s);
@@ -169,8 +218,9 @@ int rebuild_lists(mrtfd_batch_s* B)
         }
         pre[n] = acc;
         B->nlist[s] = n;
+        if (s == LIST_PAIR) B->pair_items = acc;
     }
-    int* wl = host.data() + NSHAPE * (B->capacity + 1) + NSHAPE * B->capacity;
+    int* wl = host.data() + NLIST * (B->capacity + 1) + NLIST * B->capacity;
     for (int k = 0; k < B->capacity; ++k) {
         if (!B->used[k] || B->L >= B->slot[k].stop) continue;
         const mrtfd_params& p = B->prm[k];
@@ -183,67 +233,143 @@ int rebuild_lists(mrtfd_batch_s* B)
     return MRTFD_OK;
 }
 
+// One launch over work list s at step counter L.
 template <int LIM, typename T>
-int launch_shape(mrtfd_batch_s* B, int s, long items)
+int launch_list(mrtfd_batch_s* B, int s, long items, long L)
 {
     const int* pre = prefix_dev(B, s);
     const int* lst = list_dev(B, s);
     const int n = B->nlist[s];
-    if (s == MARCH) {
+    if (s == LIST_PAIR) {
+        // persistent pairs, a multiple of 8 blocks for the XCD-aware numbering
+        long blocks = std::min<long>(items, B->pair_blocks);
+        blocks = (blocks + 7) / 8 * 8;
+        hipLaunchKernelGGL((k_march2_batch<LIM, T>), dim3((int)blocks), dim3(2 * MW), 0, B->stream, B->d_slot, pre,
+                           lst, n, L, B->R);
+        HIPCHK(hipGetLastError());
+        return MRTFD_OK;
+    }
+    if (s == MARCH || s == LIST_SINGLE) {
         // persistent wavefronts; the XCD-aware numbering needs a multiple of 8 blocks
         long blocks = std::min<long>((items + MWPB - 1) / MWPB, B->march_blocks);
         blocks = (blocks + 7) / 8 * 8;
         hipLaunchKernelGGL((k_march_batch<LIM, T>), dim3((int)blocks), dim3(MW * MWPB), 0, B->stream, B->d_slot, pre,
-                           lst, n, B->L);
+                           lst, n, L, B->R);
         HIPCHK(hipGetLastError());
         return MRTFD_OK;
     }
     const int grid = (int)std::min<long>(items, B->max_blocks);
     switch (s) {
-    case 0: hipLaunchKernelGGL((k_step_batch<LIM, T, 32, 8, false>), dim3(grid), dim3(256), 0, B->stream, B->d_slot, pre, lst, n, B->L); break;
-    case 1: hipLaunchKernelGGL((k_step_batch<LIM, T, 64, 4, false>), dim3(grid), dim3(256), 0, B->stream, B->d_slot, pre, lst, n, B->L); break;
-    case 2: hipLaunchKernelGGL((k_step_batch<LIM, T, 128, 2, false>), dim3(grid), dim3(256), 0, B->stream, B->d_slot, pre, lst, n, B->L); break;
-    default: hipLaunchKernelGGL((k_step_batch<LIM, T, 256, 1, true>), dim3(grid), dim3(256), 0, B->stream, B->d_slot, pre, lst, n, B->L); break;
+    case 0: hipLaunchKernelGGL((k_step_batch<LIM, T, 32, 8, false>), dim3(grid), dim3(256), 0, B->stream, B->d_slot, pre, lst, n, L); break;
+    case 1: hipLaunchKernelGGL((k_step_batch<LIM, T, 64, 4, false>), dim3(grid), dim3(256), 0, B->stream, B->d_slot, pre, lst, n, L); break;
+    case 2: hipLaunchKernelGGL((k_step_batch<LIM, T, 128, 2, false>), dim3(grid), dim3(256), 0, B->stream, B->d_slot, pre, lst, n, L); break;
+    default: hipLaunchKernelGGL((k_step_batch<LIM, T, 256, 1, true>), dim3(grid), dim3(256), 0, B->stream, B->d_slot, pre, lst, n, L); break;
     }
     HIPCHK(hipGetLastError());
     return MRTFD_OK;
 }
 
 template <typename T>
-int launch_step_batch_t(mrtfd_batch_s* B)
+int launch_lists(mrtfd_batch_s* B, const int* lists, int nl, long L)
+{
+    for (int q = 0; q < nl; ++q) {
+        const int s = lists[q];
+        if (!B->nlist[s]) continue;
+        long items = 0;
+        for (int k = 0; k < B->capacity; ++k) {
+            if (!B->used[k] || B->L >= B->slot[k].stop) continue;
+            const int cls = (s == LIST_PAIR || s == LIST_SINGLE) ? MARCH : s;
+            if (B->shape[k] != cls || (s == LIST_PAIR && !B->slot[k].pair) || (s == LIST_SINGLE && B->slot[k].pair))
+                continue;
+            items += items_of(B->slot[k].a, s);
+        }
+        int rc = 0;
+        switch (B->limiter) {
+        case 0: rc = launch_list<0, T>(B, s, items, L); break;
+        case 1: rc = launch_list<1, T>(B, s, items, L); break;
+        case 2: rc = launch_list<2, T>(B, s, items, L); break;
+        default: rc = launch_list<3, T>(B, s, items, L); break;
+        }
+        if (rc) return rc;
+    }
+    if (B->nwall) {
+        hipLaunchKernelGGL((k_wall_batch<T>), dim3(B->nwall), dim3(256), 0, B->stream, B->d_slot, wall_dev(B), L);
+        HIPCHK(hipGetLastError());
+    }
+    return MRTFD_OK;
+}
+
+// Whether the next round can take two steps: some slot steps in pairs,
+// every such slot has two steps left, and the two-step launch fills the
+// device twice over.  (A pair band's 32 rows take 38 barrier-bound
+// iterations for two steps, against about 26 rows walked by two one-step
+// launches of 12-row bands, so a batch too small to fill the device is
+// faster one step at a time: the lightly loaded served stream's median
+// latency rose from 0.69 s to 1.10 s with pairs regardless.)
+// Two-step work items a two-step round needs, in multiples of the resident
+// pairs (measured on the served stream at 15 requests/s: median / 99th
+// percentile latency 0.80 / 2.52 s with 1, 0.75 / 2.16 s with 2, 0.72 /
+// 2.16 s with 4, against 0.69 / 2.12 s without two-step rounds; the
+// overloaded stream gains 22 % throughput with any of them).
+#ifndef MARCH2_BATCH_FILL
+#define MARCH2_BATCH_FILL 2
+#endif
+bool two_step_round_ok(const mrtfd_batch_s* B)
+{
+    if (B->per_launch != 2 || B->pair_items < (long)MARCH2_BATCH_FILL * B->pair_blocks) return false;
+    bool any = false;
+    for (int k = 0; k < B->capacity; ++k) {
+        const BatchSlot& sl = B->slot[k];
+        if (!B->used[k] || !sl.pair || B->L >= sl.stop) continue;
+        if (sl.stop - B->L < 2) return false;
+        any = true;
+    }
+    return any;
+}
+
+// One round: one step of every stepping slot, or (two = true) two steps,
+// the pair slots in one launch and the others in two one-step launches.
+template <typename T>
+int launch_round_t(mrtfd_batch_s* B, bool two)
 {
     if (B->dirty) {
         int rc = rebuild_lists(B);
         if (rc) return rc;
     }
-    for (int s = 0; s < NSHAPE; ++s) {
-        if (!B->nlist[s]) continue;
-        long items = 0;
-        for (int k = 0; k < B->capacity; ++k)
-            if (B->used[k] && B->shape[k] == s && B->L < B->slot[k].stop) items += items_of(B->slot[k].a, s);
-        int rc = 0;
-        switch (B->limiter) {
-        case 0: rc = launch_shape<0, T>(B, s, items); break;
-        case 1: rc = launch_shape<1, T>(B, s, items); break;
-        case 2: rc = launch_shape<2, T>(B, s, items); break;
-        default: rc = launch_shape<3, T>(B, s, items); break;
-        }
+    const long L0 = B->L;
+    if (two) {
+        const int pairs[] = {LIST_PAIR};
+        int rc = launch_lists<T>(B, pairs, 1, L0);
         if (rc) return rc;
+        const int others[] = {0, 1, 2, 3, LIST_SINGLE};
+        for (int h = 0; h < 2; ++h) {
+            rc = launch_lists<T>(B, others, 5, L0 + h);
+            if (rc) return rc;
+        }
+        B->L += 2;
+    } else {
+        const int all[] = {0, 1, 2, 3, MARCH};
+        int rc = launch_lists<T>(B, all, 5, L0);
+        if (rc) return rc;
+        B->L += 1;
     }
-    if (B->nwall) {
-        hipLaunchKernelGGL((k_wall_batch<T>), dim3(B->nwall), dim3(256), 0, B->stream, B->d_slot, wall_dev(B), B->L);
-        HIPCHK(hipGetLastError());
+    B->R += 1;
+    // slots whose budget just ran out leave the work lists; pair slots
+    // keep the round at which they stopped
+    for (int k = 0; k < B->capacity; ++k) {
+        if (!B->used[k]) continue;
+        const long stop = B->slot[k].stop;
+        if (stop > L0 && stop <= B->L) {
+            B->dirty = true;
+            if (B->slot[k].pair) B->rstop[k] = B->R;
+        }
     }
-    B->L += 1;
-    // slots whose budget just ran out leave the work lists
-    for (int k = 0; k < B->capacity; ++k)
-        if (B->used[k] && B->slot[k].stop == B->L) B->dirty = true;
     return MRTFD_OK;
 }
 
-int launch_step_batch(mrtfd_batch_s* B)
+int launch_round(mrtfd_batch_s* B, bool two)
 {
-    return (B->precision == MRTFD_FP32_STORAGE) ? launch_step_batch_t<float>(B) : launch_step_batch_t<double>(B);
+    return (B->precision == MRTFD_FP32_STORAGE) ? launch_round_t<float>(B, two) : launch_round_t<double>(B, two);
 }
 
 int ensure_staging(mrtfd_batch_s* B, size_t bytes)
@@ -263,13 +389,6 @@ int ensure_staging(mrtfd_batch_s* B, size_t bytes)
     return MRTFD_OK;
 }
 
-// Buffer holding the slot's current state.
-int current_buffer(const mrtfd_batch_s* B, int k)
-{
-    const long done = std::min(B->L, B->slot[k].stop) - B->slot[k].start;
-    return (int)(done & 1);
-}
-
 template <typename T>
 const void* march_batch_kernel(int limiter)
 {
@@ -278,6 +397,17 @@ const void* march_batch_kernel(int limiter)
     case 1: return (const void*)k_march_batch<1, T>;
     case 2: return (const void*)k_march_batch<2, T>;
     default: return (const void*)k_march_batch<3, T>;
+    }
+}
+
+template <typename T>
+const void* pair_batch_kernel(int limiter)
+{
+    switch (limiter) {
+    case 0: return (const void*)k_march2_batch<0, T>;
+    case 1: return (const void*)k_march2_batch<1, T>;
+    case 2: return (const void*)k_march2_batch<2, T>;
+    default: return (const void*)k_march2_batch<3, T>;
     }
 }
 
@@ -302,8 +432,10 @@ int assign_shape(mrtfd_batch_s* B, int k, int s)
 {
     const int old = B->shape[k];
     if (old == s) return MRTFD_OK;
+    const int cur = current_buffer(B, k);
     B->shape[k] = s;
     set_args(B, k);
+    rebase(B, k, cur);
     int rc = upload_slot(B, k);
     if (rc) return rc;
     if (old == MARCH) {
@@ -362,11 +494,13 @@ int mrtfd_batch_create(int capacity, int precision, int limiter, void* hip_strea
     B->blk.resize(capacity);
     B->used.assign(capacity, 0);
     B->shape.assign(capacity, 0);
+    B->rstop.assign(capacity, LONG_MAX);
+    B->per_launch = 2;
     for (int s = 0; s < NSHAPE; ++s) {
         B->cost[s] = DEFAULT_COST[s];
         B->launch_us[s] = 10.0;
     }
-    const size_t lists = (size_t)(NSHAPE * (capacity + 1) + NSHAPE * capacity + capacity) * sizeof(int);
+    const size_t lists = (size_t)(NLIST * (capacity + 1) + NLIST * capacity + capacity) * sizeof(int);
     if (hipMalloc(&B->d_slot, capacity * sizeof(BatchSlot)) != hipSuccess ||
         hipMalloc(&B->d_blocks, capacity * sizeof(Blocks)) != hipSuccess ||
         hipMalloc(&B->d_flags, capacity * sizeof(int)) != hipSuccess || hipMalloc(&B->d_lists, lists) != hipSuccess ||
@@ -387,6 +521,10 @@ int mrtfd_batch_create(int capacity, int precision, int limiter, void* hip_strea
     const void* km = (precision == MRTFD_FP32_STORAGE) ? march_batch_kernel<float>(limiter) : march_batch_kernel<double>(limiter);
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, km, MW * MWPB, 0) != hipSuccess) (void)hipGetLastError();
     B->march_blocks = std::max(nb, 1) * ncu;
+    nb = 0;
+    const void* kp = (precision == MRTFD_FP32_STORAGE) ? pair_batch_kernel<float>(limiter) : pair_batch_kernel<double>(limiter);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kp, 2 * MW, 0) != hipSuccess) (void)hipGetLastError();
+    B->pair_blocks = std::max(nb, 1) * ncu;
     B->dirty = true;
     *out = B;
     return MRTFD_OK;
@@ -443,6 +581,7 @@ int mrtfd_batch_add(mrtfd_batch_t B, const mrtfd_params* p, const double* rho, c
     set_args(B, k);
     B->slot[k].start = B->L;
     B->slot[k].stop = (nsteps < 0) ? LONG_MAX : B->L + nsteps;
+    rebase(B, k, 0);   // the state starts in buffer 0
     B->used[k] = 1;
     rc = [&]() -> int {
         HIPCHK(hipMemcpyAsync(B->d_blocks + k, &B->blk[k], sizeof(Blocks), hipMemcpyHostToDevice, B->stream));
@@ -498,6 +637,7 @@ int mrtfd_batch_set_steps(mrtfd_batch_t B, int k, long nsteps)
     }
     B->slot[k].start = B->L;
     B->slot[k].stop = (nsteps < 0) ? LONG_MAX : B->L + nsteps;
+    rebase(B, k, 0);
     rc = upload_slot(B, k);
     if (rc) return rc;
     B->dirty = true;
@@ -508,10 +648,41 @@ int mrtfd_batch_step(mrtfd_batch_t B, long nsteps)
 {
     if (!B) return fail(MRTFD_EINVAL, "NULL batch");
     if (nsteps < 0) return fail(MRTFD_EINVAL, "nsteps < 0");
-    for (long s = 0; s < nsteps; ++s) {
-        int rc = launch_step_batch(B);
+    for (long s = 0; s < nsteps;) {
+        if (B->dirty) {
+            int rc = rebuild_lists(B);
+            if (rc) return rc;
+        }
+        const bool two = nsteps - s >= 2 && two_step_round_ok(B);
+        int rc = launch_round(B, two);
+        if (rc) return rc;
+        s += two ? 2 : 1;
+    }
+    return MRTFD_OK;
+}
+
+int mrtfd_batch_get_steps_per_launch(mrtfd_batch_t B, int* k)
+{
+    if (!B || !k) return fail(MRTFD_EINVAL, "NULL argument");
+    *k = B->per_launch;
+    return MRTFD_OK;
+}
+
+int mrtfd_batch_set_steps_per_launch(mrtfd_batch_t B, int k)
+{
+    if (!B) return fail(MRTFD_EINVAL, "NULL batch");
+    if (k != 1 && k != 2) return fail(MRTFD_EINVAL, "steps per launch must be 1 or 2, got %d", k);
+    if (k == B->per_launch) return MRTFD_OK;
+    B->per_launch = k;
+    for (int q = 0; q < B->capacity; ++q) {
+        if (!B->used[q]) continue;
+        const int cur = current_buffer(B, q);
+        B->slot[q].pair = pair_capable(B, q) ? 1 : 0;
+        rebase(B, q, cur);
+        int rc = upload_slot(B, q);
         if (rc) return rc;
     }
+    B->dirty = true;
     return MRTFD_OK;
 }
 
@@ -621,6 +792,7 @@ int mrtfd_batch_set_f(mrtfd_batch_t B, int k, const double* f, int on_device)
     const long remaining = (B->slot[k].stop == LONG_MAX) ? -1 : std::max(0L, B->slot[k].stop - B->L);
     B->slot[k].start = B->L;
     B->slot[k].stop = (remaining < 0) ? LONG_MAX : B->L + remaining;
+    rebase(B, k, 0);
     rc = upload_slot(B, k);
     if (rc) return rc;
     rc = init_slot(B, k, nullptr, src);

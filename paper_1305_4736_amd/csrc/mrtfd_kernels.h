@@ -495,14 +495,19 @@ __global__ void k_scatter(T* __restrict__ f, const double* __restrict__ in, Step
 // ---------------------------------------------------------------------------
 // Batched form: many independent instances advance in one persistent launch
 // per tile-shape class.  Each slot carries its own arguments and ping-pong
-// buffers; a launch counter L decides which buffer is current
-// ((L - start) mod 2) and whether the slot still steps (L < stop), so
-// slots join, finish and leave without per-launch uploads.
+// buffers.  The batch counts steps (L) and rounds (R): a round is one step,
+// or two steps for the slots that take two per launch ("pair" slots) while
+// the others take two one-step launches.  A slot's current buffer is the
+// parity of its clock (R for pair slots, L for the others) against pstart,
+// and it steps while L < stop, so slots join, finish and leave without
+// per-launch uploads.
 struct BatchSlot {
     StepArgs a;
     void* buf[2];
-    long start;   // launch counter at which the slot's buffer 0 held its state
-    long stop;    // first launch counter at which the slot no longer steps
+    long start;   // step counter at which the slot's step count starts
+    long stop;    // first step counter at which the slot no longer steps
+    long pstart;  // clock value at which buffer 0 held the slot's state
+    int pair;     // 1: the slot's clock is R (it takes two steps per launch in two-step rounds)
 };
 
 // Work items are the tiles of the listed slots, numbered slot after slot
@@ -523,7 +528,7 @@ __global__ void __launch_bounds__(TXW * BYR, 1) k_step_batch(const BatchSlot* __
         }
         const BatchSlot& sl = slots[list[lo]];
         if (L < sl.stop) {
-            const int par = (int)((L - sl.start) & 1);
+            const int par = (int)((L - sl.pstart) & 1);   // never a pair slot
             step_tile<LIM, T, TXW, BYR, FLAT>((const T*)sl.buf[par], (T*)sl.buf[par ^ 1], sl.a, item - prefix[lo], sm_);
         }
         __syncthreads();   // LDS is reused by the next item
@@ -536,7 +541,7 @@ __global__ void k_wall_batch(const BatchSlot* __restrict__ slots, const int* __r
 {
     const BatchSlot& sl = slots[wlist[blockIdx.x]];
     if (L >= sl.stop) return;
-    const int par = (int)((L - sl.start) & 1);
+    const int par = (int)((L - sl.pstart) & 1);           // slots with walls are never pair slots
     T* f = (T*)sl.buf[par ^ 1];
     for (int axis = 0; axis < 2; ++axis) {
         if (sl.a.bc[2 * axis] != BC_WALL && sl.a.bc[2 * axis + 1] != BC_WALL) continue;

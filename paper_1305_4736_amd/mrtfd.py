@@ -282,6 +282,8 @@ _lib.mrtfd_batch_add.argtypes = [_B, ctypes.POINTER(_Params), _vp, _vp, _vp, _vp
 _lib.mrtfd_batch_remove.argtypes = [_B, ctypes.c_int]
 _lib.mrtfd_batch_set_steps.argtypes = [_B, ctypes.c_int, ctypes.c_long]
 _lib.mrtfd_batch_step.argtypes = [_B, ctypes.c_long]
+_lib.mrtfd_batch_set_steps_per_launch.argtypes = [_B, ctypes.c_int]
+_lib.mrtfd_batch_get_steps_per_launch.argtypes = [_B, ctypes.POINTER(ctypes.c_int)]
 _lib.mrtfd_batch_step_timed.argtypes = [_B, ctypes.c_long, _dp]
 _lib.mrtfd_batch_steps_done.argtypes = [_B, ctypes.c_int]
 _lib.mrtfd_batch_steps_done.restype = ctypes.c_long
@@ -357,6 +359,17 @@ class Batch:
     def step(self, nsteps: int = 1):
         _check(_lib.mrtfd_batch_step(self._b, int(nsteps)))
         return self
+
+    @property
+    def steps_per_launch(self) -> int:
+        """2: slots that can take two steps per launch in two-step rounds; 1: one."""
+        k = ctypes.c_int()
+        _check(_lib.mrtfd_batch_get_steps_per_launch(self._b, ctypes.byref(k)))
+        return k.value
+
+    @steps_per_launch.setter
+    def steps_per_launch(self, k: int):
+        _check(_lib.mrtfd_batch_set_steps_per_launch(self._b, int(k)))
 
     def step_timed(self, nsteps: int) -> float:
         ms = ctypes.c_double(0.0)

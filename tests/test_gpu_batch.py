@@ -170,6 +170,52 @@ def test_budgets_and_membership_changes(lib):
         assert b.steps_done(slots[1]) == 3
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_two_step_rounds_match_one_step(lib, precision):
+    # slots that take two steps per launch (strips, no walls, >= 8 rows)
+    # next to ones that cannot (walls, short, tiles); odd and even budgets,
+    # a restart and a class change mid-run, a slot joining late; the
+    # 4096 x 1024 instance makes the two-step work fill the device twice
+    # over, which two-step rounds need (it is compared by its macros)
+    cases = mixed_cases() + [W.random_smooth(300, 150, seed=21, bcs=[E, O, P, P], jumps=True),
+                             W.random_smooth(90, 64, seed=22, bcs=[O, O, O, O], jumps=True),
+                             W.random_smooth(4096, 1024, seed=24, bcs=[E, O, P, P], jumps=True)]
+    cases = [dict(c, params=dict(c["params"], precision=precision)) for c in cases]
+    budgets = [7, 40, 33, -1, 40, 0, 21, 40, 39, 40, -1]
+    late = W.random_smooth(120, 48, seed=23, bcs=[P, P, P, P], jumps=True)
+    late = dict(late, params=dict(late["params"], precision=precision))
+    out = {}
+    for k in (1, 2):
+        with lib.Batch(len(cases) + 1, precision=precision) as b:
+            b.steps_per_launch = k
+            assert b.steps_per_launch == k
+            slots = add_all(b, cases, budgets)
+            b.step(11)
+            b.set_steps(slots[3], 9)
+            b.set_shape(slots[7], "tile32x8")
+            s_late = b.add(late["params"], late["rho"], late["ux"], late["uy"], late["T"], nsteps=25)
+            b.step(13)
+            b.set_shape(slots[7], "strips")
+            b.step(20)
+            out[k] = ([b.macros(s) if s == slots[10] else b.get_f(s) for s in slots + [s_late]],
+                      [b.steps_done(s) for s in slots + [s_late]])
+    assert out[1][1] == out[2][1]
+    assert out[2][1] == [7, 40, 33, 9, 40, 0, 21, 40, 39, 40, 44, 25]
+    for a, c, case in zip(out[1][0], out[2][0], cases + [late]):
+        if isinstance(a, tuple):
+            assert all(np.array_equal(x, y) for x, y in zip(a, c)), case["name"]
+        else:
+            assert np.array_equal(a, c), case["name"]
+    # and against one instance alone
+    for idx in (8, 9):
+        c = cases[idx]
+        with lib.Solver(c["params"]) as single:
+            single.steps_per_launch = 1
+            single.init(c["rho"], c["ux"], c["uy"], c["T"])
+            single.step(budgets[idx])
+            assert np.array_equal(single.get_f(), out[2][0][idx]), c["name"]
+
+
 def test_autotune_keeps_results(lib):
     cases = mixed_cases()
     n = 12
