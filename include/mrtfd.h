@@ -176,7 +176,8 @@ int mrtfd_constants(double eta0, double* M, double* Minv);
 /* ------------------------------------------------------------------------
  * Batched form: many independent instances (different grids, states,
  * rates, b and boundaries; one precision and one limiter per batch) advance
- * together, one persistent launch per tile-shape class per step.  The
+ * together, one persistent launch per tile-shape class per step (or per
+ * two steps, for the instances that take two steps per launch).  The
  * per-instance arithmetic is the one above, so a slot's result does not
  * depend on the other slots.  Slots own their device state (allocated from
  * the stream-ordered pool on the batch's stream) and a step budget; slots
@@ -202,9 +203,11 @@ int mrtfd_batch_remove(mrtfd_batch_t b, int slot);
 /* New budget for a slot, counted from now (nsteps < 0: unlimited). */
 int mrtfd_batch_set_steps(mrtfd_batch_t b, int slot, long nsteps);
 
-/* nsteps launches; each advances every slot that still has budget by one
- * step.  Asynchronous on the batch's stream.  The timed form synchronises
- * and reports the device time of those launches (HIP events). */
+/* Advance every slot that still has budget by nsteps steps (each slot stops
+ * when its budget is spent), in rounds of one step, or of two steps where
+ * mrtfd_batch_set_steps_per_launch allows.  Asynchronous on the batch's
+ * stream.  The timed form synchronises and reports the device time of
+ * those launches (HIP events). */
 int mrtfd_batch_step(mrtfd_batch_t b, long nsteps);
 
 /* Steps per launch of the batch's two-step rounds: with k = 2 (default),
