@@ -187,6 +187,9 @@ def test_two_step_rounds_match_one_step(lib, precision):
     out = {}
     for k in (1, 2):
         with lib.Batch(len(cases) + 1, precision=precision) as b:
+            assert b.steps_per_launch == 2
+            with pytest.raises(lib.MRTFDError):
+                b.steps_per_launch = 3
             b.steps_per_launch = k
             assert b.steps_per_launch == k
             slots = add_all(b, cases, budgets)

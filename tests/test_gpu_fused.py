@@ -8,10 +8,11 @@ single step).  Cases cover every boundary kind on each axis (periodic
 ghosts computed by translation, equilibrium ghosts passed through, outflow
 ghosts read at their source lane or row), grids narrower than a strip,
 ragged strips, one-row and few-row grids (a band reaching both edges),
-launches with many bands, both storage precisions and all four limiters.  Walls are rejected for fusion.  The
-fused path is also compared with the oracle directly (every boundary kind,
-both precisions), and the other GPU tests run it wherever it is the default
-(FP64 on large grids, e.g. the full 4096 x 1024 shock-interface windows).
+launches with many bands, both storage precisions and all four limiters.
+Walls are rejected for fusion.  The fused path is also compared with the
+oracle directly (every boundary kind, both precisions), and the other GPU
+tests run it wherever it is the default (large grids, e.g. the full
+4096 x 1024 shock-interface windows).
 """
 import numpy as np
 import pytest
