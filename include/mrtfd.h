@@ -111,13 +111,14 @@ int mrtfd_init(mrtfd_t h, const double* rho, const double* ux, const double* uy,
  * level n): a fused kernel computes moments, equilibria, correction,
  * collision, limited fluxes and the update.  On grids large enough to
  * fill the device (FP64 from about 1024 x 256 nodes, FP32 storage from
- * about 1024 x 512), where supported (no NEE wall side, state below
+ * about 1024 x 512), where supported (no NEE wall along x, state below
  * 2 GiB), one launch takes two steps, the second reading
- * the first's rows from on-chip memory, so the state crosses HBM once per
- * two steps; an odd remainder, and handles set to one step per launch,
- * take one launch per step (the row-marching form for state buffers below
- * 2 GiB, else the LDS-tile form), followed by a small launch that refills
- * NEE walls if there are any.  Every form gives the same bits.
+ * the first's rows (wall rows along y refilled among them) from on-chip
+ * memory, so the state crosses HBM once per two steps; an odd remainder,
+ * and handles set to one step per launch, take one launch per step (the
+ * row-marching form for state buffers below 2 GiB, else the LDS-tile
+ * form).  Each launch is followed by a small launch that refills NEE walls
+ * if there are any.  Every form gives the same bits.
  * Asynchronous on the handle's stream; non-finite or unphysical nodes are
  * flagged on the device and reported by mrtfd_sync. */
 int mrtfd_step(mrtfd_t h, long nsteps);
@@ -126,8 +127,8 @@ int mrtfd_step(mrtfd_t h, long nsteps);
  * grids, where supported) fuses pairs of steps, k = 1 (the default
  * otherwise) launches once per step.  Results are bitwise the same either
  * way.  MRTFD_EINVAL for k other than 1 or 2,
- * or k = 2 on a handle with a wall side or a state of 2 GiB or more (the
- * setting is then unchanged). */
+ * or k = 2 on a handle with a wall along x or a state of 2 GiB or more
+ * (the setting is then unchanged). */
 int mrtfd_set_steps_per_launch(mrtfd_t h, int k);
 int mrtfd_get_steps_per_launch(mrtfd_t h, int* k);
 
@@ -211,7 +212,7 @@ int mrtfd_batch_set_steps(mrtfd_batch_t b, int slot, long nsteps);
 int mrtfd_batch_step(mrtfd_batch_t b, long nsteps);
 
 /* Steps per launch of the batch's two-step rounds: with k = 2 (default),
- * slots in the strip class without walls and with at least 8 rows take two
+ * slots in the strip class without walls along x and with at least 8 rows take two
  * steps per launch (the second step reading the first's rows from on-chip
  * memory) in rounds where every such slot has two steps left and their
  * work fills the device (a smaller batch is faster one step at a time);

@@ -2,8 +2,8 @@
 // lattice-Boltzmann step (arXiv:1305.4736): single-instance entry points.
 //
 // A time step is one pass of a fused step kernel (mrtfd_march.h: the
-// row-marching form, one step per launch or, on large grids without walls,
-// two steps per launch through an LDS ring of rows): each node's new
+// row-marching form, one step per launch or, on large grids without walls
+// along x, two steps per launch through an LDS ring of rows): each node's new
 // populations come, from level n only, from its moments
 // and macroscopic state (Sec. II), the velocity of its four axis neighbours
 // (energy-flux correction, Sec. II), the equilibria (Appendix), the relaxed
@@ -12,8 +12,8 @@
 // eqs.) and the new populations.  The march reads periodic and outflow
 // sides at their source nodes (the LDS-tile form for states of 2 GiB and
 // more writes those ghost images instead); walls, if any, are refilled by
-// a small kernel after the step; equilibrium ghosts are constant and
-// written once.
+// a small kernel after each launch (and, inside a two-step launch, in its
+// ring of rows); equilibrium ghosts are constant and written once.
 #include <hip/hip_runtime.h>
 
 #include <new>
@@ -64,12 +64,13 @@ void fill_args(mrtfd_s* h)
 }
 
 // Whether this instance can take two steps per launch: the march form
-// (state below 2 GiB) and no walls (their refill sits between steps).
+// (state below 2 GiB) and no walls along x (walls along y are refilled
+// inside the pair, whose bands all walk up).
 bool pair_supported(const mrtfd_s* h)
 {
     const StepArgs& a = h->args;
-    for (int s = 0; s < 4; ++s)
-        if (a.bc[s] == BC_WALL) return false;
+    if (a.bc[0] == BC_WALL || a.bc[1] == BC_WALL) return false;
+    if (MARCH2_ALTERNATE && (a.bc[2] == BC_WALL || a.bc[3] == BC_WALL)) return false;
     const bool fits = (h->p.precision == MRTFD_FP32_STORAGE) ? march_fits<float>(a) : march_fits<double>(a);
     return fits && a.x1 > a.x0 && a.y1 > a.y0;
 }
@@ -133,6 +134,21 @@ int ensure_staging(mrtfd_s* h, size_t bytes)
     return MRTFD_OK;
 }
 
+// Wall rows and their ghosts of the new state fout, from the rows next to
+// the walls (after a one- or two-step launch).
+template <typename T>
+int refill_walls(mrtfd_s* h, T* fout)
+{
+    const StepArgs& a = h->args;
+    for (int axis = 0; axis < 2; ++axis) {
+        if (a.bc[2 * axis] != BC_WALL && a.bc[2 * axis + 1] != BC_WALL) continue;
+        const int n = 2 * ((axis == 0) ? a.ny : a.nx);
+        hipLaunchKernelGGL((k_fill<T>), dim3((n + 127) / 128), dim3(128), 0, h->stream, fout, a, axis, 1);
+        HIPCHK(hipGetLastError());
+    }
+    return MRTFD_OK;
+}
+
 template <typename T>
 int launch_step_t(mrtfd_s* h)
 {
@@ -161,12 +177,8 @@ int launch_step_t(mrtfd_s* h)
             }
         }
         HIPCHK(hipGetLastError());
-        for (int axis = 0; axis < 2; ++axis) {
-            if (a.bc[2 * axis] != BC_WALL && a.bc[2 * axis + 1] != BC_WALL) continue;
-            const int n = 2 * ((axis == 0) ? a.ny : a.nx);
-            hipLaunchKernelGGL((k_fill<T>), dim3((n + 127) / 128), dim3(128), 0, h->stream, fout, a, axis, 1);
-            HIPCHK(hipGetLastError());
-        }
+        int rc = refill_walls<T>(h, fout);
+        if (rc) return rc;
     }
     h->cur = 1 - h->cur;
     return MRTFD_OK;
@@ -192,6 +204,8 @@ int launch_pair_t(mrtfd_s* h)
     default: hipLaunchKernelGGL((k_march2<3, T>), grid, block, 0, h->stream, fin, fout, h->args_dev); break;
     }
     HIPCHK(hipGetLastError());
+    int rc = refill_walls<T>(h, fout);
+    if (rc) return rc;
     h->cur = 1 - h->cur;
     return MRTFD_OK;
 }
@@ -366,7 +380,7 @@ int mrtfd_set_steps_per_launch(mrtfd_t h, int k)
     if (!h) return fail(MRTFD_EINVAL, "NULL handle");
     if (k != 1 && k != 2) return fail(MRTFD_EINVAL, "steps per launch must be 1 or 2, got %d", k);
     if (k == 2 && !pair_supported(h))
-        return fail(MRTFD_EINVAL, "two steps per launch need no wall sides and a state below 2 GiB");
+        return fail(MRTFD_EINVAL, "two steps per launch need no walls along x and a state below 2 GiB");
     h->per_launch = k;
     return MRTFD_OK;
 }

@@ -13,7 +13,7 @@
 // Shape classes: the row-marching strips of mrtfd_march.h (60 output
 // columns x bands of up to 12 rows per wavefront), and LDS tiles of 256
 // threads: 32 x 8, 64 x 4, 128 x 2, and 256 x 1 rows for one-row instances.
-// Strip slots without walls and with at least 8 rows take two steps per
+// Strip slots without walls along x and with at least 8 rows take two steps per
 // launch (k_march2_batch, bands of up to 32 rows) in two-step rounds, which
 // the batch runs while every such slot has two steps left; the other slots
 // then take two one-step launches.
@@ -96,6 +96,7 @@ struct mrtfd_batch_s {
     int* d_flags;
     int* d_lists;                       // NLIST x (capacity + 1) prefixes, then NLIST x capacity slot lists, then walls
     int nlist[NLIST], nwall;
+    int nwall_pair;                     // the wall list holds the pair slots' first
     bool dirty;
     long L;                             // steps taken by the batch
     long R;                             // rounds (one or two steps each)
@@ -151,13 +152,13 @@ int pick_shape(const mrtfd_batch_s* B, const mrtfd_params& p)
 }
 
 // Whether slot k takes two steps per launch in two-step rounds: a strip
-// slot without walls and with at least MARCH2_BATCH_MIN_ROWS rows.
+// slot without walls along x and with at least MARCH2_BATCH_MIN_ROWS rows
+// (the batched pairs walk up, so walls along y are refilled inside them).
 bool pair_capable(const mrtfd_batch_s* B, int k)
 {
     if (B->per_launch != 2 || B->shape[k] != MARCH) return false;
     const mrtfd_params& p = B->prm[k];
-    for (int q = 0; q < 4; ++q)
-        if (p.bc[q].kind == BC_WALL) return false;
+    if (p.bc[0].kind == BC_WALL || p.bc[1].kind == BC_WALL) return false;
     return p.ny >= MARCH2_BATCH_MIN_ROWS;
 }
 
@@ -220,13 +221,17 @@ int rebuild_lists(mrtfd_batch_s* B)
         B->nlist[s] = n;
         if (s == LIST_PAIR) B->pair_items = acc;
     }
+    // slots with walls: the pair slots, then the others
     int* wl = host.data() + NLIST * (B->capacity + 1) + NLIST * B->capacity;
-    for (int k = 0; k < B->capacity; ++k) {
-        if (!B->used[k] || B->L >= B->slot[k].stop) continue;
-        const mrtfd_params& p = B->prm[k];
-        bool walls = false;
-        for (int q = 0; q < 4; ++q) walls |= (p.bc[q].kind == BC_WALL);
-        if (walls) wl[B->nwall++] = k;
+    for (int pass = 1; pass >= 0; --pass) {
+        for (int k = 0; k < B->capacity; ++k) {
+            if (!B->used[k] || B->L >= B->slot[k].stop || B->slot[k].pair != pass) continue;
+            const mrtfd_params& p = B->prm[k];
+            bool walls = false;
+            for (int q = 0; q < 4; ++q) walls |= (p.bc[q].kind == BC_WALL);
+            if (walls) wl[B->nwall++] = k;
+        }
+        if (pass == 1) B->nwall_pair = B->nwall;
     }
     HIPCHK(hipMemcpyAsync(B->d_lists, host.data(), host.size() * sizeof(int), hipMemcpyHostToDevice, B->stream));
     B->dirty = false;
@@ -269,8 +274,11 @@ int launch_list(mrtfd_batch_s* B, int s, long items, long L)
     return MRTFD_OK;
 }
 
+// Wall refill after a launch: the pair slots' walls, the others', or all.
+enum { WALLS_PAIR, WALLS_SINGLE, WALLS_ALL };
+
 template <typename T>
-int launch_lists(mrtfd_batch_s* B, const int* lists, int nl, long L)
+int launch_lists(mrtfd_batch_s* B, const int* lists, int nl, long L, int walls)
 {
     for (int q = 0; q < nl; ++q) {
         const int s = lists[q];
@@ -292,8 +300,11 @@ int launch_lists(mrtfd_batch_s* B, const int* lists, int nl, long L)
         }
         if (rc) return rc;
     }
-    if (B->nwall) {
-        hipLaunchKernelGGL((k_wall_batch<T>), dim3(B->nwall), dim3(256), 0, B->stream, B->d_slot, wall_dev(B), L);
+    const int w0 = (walls == WALLS_SINGLE) ? B->nwall_pair : 0;
+    const int w1 = (walls == WALLS_PAIR) ? B->nwall_pair : B->nwall;
+    if (w1 > w0) {
+        hipLaunchKernelGGL((k_wall_batch<T>), dim3(w1 - w0), dim3(256), 0, B->stream, B->d_slot, wall_dev(B) + w0,
+                           L, B->R);
         HIPCHK(hipGetLastError());
     }
     return MRTFD_OK;
@@ -339,17 +350,17 @@ int launch_round_t(mrtfd_batch_s* B, bool two)
     const long L0 = B->L;
     if (two) {
         const int pairs[] = {LIST_PAIR};
-        int rc = launch_lists<T>(B, pairs, 1, L0);
+        int rc = launch_lists<T>(B, pairs, 1, L0, WALLS_PAIR);
         if (rc) return rc;
         const int others[] = {0, 1, 2, 3, LIST_SINGLE};
         for (int h = 0; h < 2; ++h) {
-            rc = launch_lists<T>(B, others, 5, L0 + h);
+            rc = launch_lists<T>(B, others, 5, L0 + h, WALLS_SINGLE);
             if (rc) return rc;
         }
         B->L += 2;
     } else {
         const int all[] = {0, 1, 2, 3, MARCH};
-        int rc = launch_lists<T>(B, all, 5, L0);
+        int rc = launch_lists<T>(B, all, 5, L0, WALLS_ALL);
         if (rc) return rc;
         B->L += 1;
     }

@@ -212,7 +212,8 @@ __host__ __device__ __forceinline__ void inverse_nc(const BT& B, const double* w
 }
 
 // v = M^-1 w for a full moment vector.
-__host__ __device__ __forceinline__ void inverse_full(const Blocks& B, const double* w, double* v)
+template <class BT>
+__host__ __device__ __forceinline__ void inverse_full(const BT& B, const double* w, double* v)
 {
     double S[4], X[4], Y[4], D[4];
 #pragma unroll
@@ -232,7 +233,8 @@ __host__ __device__ __forceinline__ void inverse_full(const Blocks& B, const dou
 }
 
 // f^eq in velocity space from primitive variables (rho, u, T).
-__device__ __forceinline__ void feq_velocity(const Blocks& B, double b, double rho, double ux,
+template <class BT>
+__device__ __forceinline__ void feq_velocity(const BT& B, double b, double rho, double ux,
                                              double uy, double T, double* out)
 {
     double P = rho * T;
@@ -243,7 +245,8 @@ __device__ __forceinline__ void feq_velocity(const Blocks& B, double b, double r
 }
 
 // rho, u, T of a node from its 16 populations.
-__device__ __forceinline__ void macro_of(const Blocks& B, double inv_b, const double* f,
+template <class BT>
+__device__ __forceinline__ void macro_of(const BT& B, double inv_b, const double* f,
                                          double& rho, double& ux, double& uy, double& T)
 {
     Sums a = all_sums(f);

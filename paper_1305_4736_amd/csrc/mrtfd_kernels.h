@@ -63,23 +63,33 @@ __device__ __forceinline__ void load16(const T* __restrict__ f, const StepArgs& 
 
 
 // Non-equilibrium extrapolation wall from the fluid node next to it (f1):
-// wall node n_w and its two ghosts n_w + step, n_w + 2 step.
+// fw[i] is the wall node's population i; its ghosts k = 1, 2 beyond the
+// wall hold (k + 1) fw - k f1.
+template <class AT, class BT>
+__device__ __forceinline__ void wall_values(const AT& a, const BT& B, const double* f1, int side, double* fw)
+{
+    double r1, u1x, u1y, T1;
+    macro_of(B, a.inv_b, f1, r1, u1x, u1y, T1);
+    const double st3 = a.side[side][3];
+    double rw = r1 * T1 / st3;             // carry the pressure over: rho_w T_w = rho_1 T_1
+    double ew[NQ], e1[NQ];
+    feq_velocity(B, a.b, rw, a.side[side][1], a.side[side][2], st3, ew);
+    feq_velocity(B, a.b, r1, u1x, u1y, T1, e1);
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) fw[i] = ew[i] + (f1[i] - e1[i]);
+}
+
+// The wall node n_w and its two ghosts n_w + step, n_w + 2 step.
 template <typename T>
 __device__ void wall_fill(const StepArgs& a, T* __restrict__ f, const double* f1, int side, long nw, long step)
 {
-    double r1, u1x, u1y, T1;
-    macro_of(*a.Bp, a.inv_b, f1, r1, u1x, u1y, T1);
-    const double* st = a.side[side];
-    double rw = r1 * T1 / st[3];           // carry the pressure over: rho_w T_w = rho_1 T_1
-    double ew[NQ], e1[NQ];
-    feq_velocity(*a.Bp, a.b, rw, st[1], st[2], st[3], ew);
-    feq_velocity(*a.Bp, a.b, r1, u1x, u1y, T1, e1);
+    double fw[NQ];
+    wall_values(a, *a.Bp, f1, side, fw);
 #pragma unroll
     for (int i = 0; i < NQ; ++i) {
-        double fw = ew[i] + (f1[i] - e1[i]);
-        f[i * a.plane + nw] = (T)fw;
-        f[i * a.plane + nw + step] = (T)(2.0 * fw - f1[i]);
-        f[i * a.plane + nw + 2 * step] = (T)(3.0 * fw - 2.0 * f1[i]);
+        f[i * a.plane + nw] = (T)fw[i];
+        f[i * a.plane + nw + step] = (T)(2.0 * fw[i] - f1[i]);
+        f[i * a.plane + nw + 2 * step] = (T)(3.0 * fw[i] - 2.0 * f1[i]);
     }
 }
 
@@ -535,13 +545,14 @@ __global__ void __launch_bounds__(TXW * BYR, 1) k_step_batch(const BatchSlot* __
     }
 }
 
-// Wall refill after a batched step: one block per listed slot with walls.
+// Wall refill after a batched launch at step counter L and round R: one
+// block per listed slot with walls, refilling the buffer the launch wrote.
 template <typename T>
-__global__ void k_wall_batch(const BatchSlot* __restrict__ slots, const int* __restrict__ wlist, long L)
+__global__ void k_wall_batch(const BatchSlot* __restrict__ slots, const int* __restrict__ wlist, long L, long R)
 {
     const BatchSlot& sl = slots[wlist[blockIdx.x]];
     if (L >= sl.stop) return;
-    const int par = (int)((L - sl.pstart) & 1);           // slots with walls are never pair slots
+    const int par = (int)(((sl.pair ? R : L) - sl.pstart) & 1);
     T* f = (T*)sl.buf[par ^ 1];
     for (int axis = 0; axis < 2; ++axis) {
         if (sl.a.bc[2 * axis] != BC_WALL && sl.a.bc[2 * axis + 1] != BC_WALL) continue;

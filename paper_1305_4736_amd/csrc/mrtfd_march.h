@@ -16,7 +16,8 @@
 // Periodic and outflow sides are read at their source nodes (a column is
 // remapped once per lane, a row once per row), so this kernel writes no
 // ghost images; equilibrium ghosts are constant and NEE walls are refilled
-// by a separate launch after the step.
+// by a separate launch after the step (and between the two steps of a pair
+// in its ring, for walls along y).
 //
 // Two steps per pass (k_march2): a block holds two wavefronts on the same
 // strip and band.  The first takes step n -> n+1 from HBM and leaves each
@@ -187,6 +188,31 @@ template <typename T>
 struct PairRing {
     T v[PRING][NQ][MW];
 };
+
+// Wall rows of step n + 1 in a pair's ring, lane `lane`: the first step's
+// row c1 next to the wall gives, by the same arithmetic as the refill after
+// a one-step launch, the wall node's row w (kmin = 0) and its first ghost
+// row w + out (kmax = 1; out = -1 on the low side, +1 on the high side).
+template <typename T>
+__device__ __forceinline__ void ring_wall(CArgs& a, PairRing<T>* ring, int lane, int side, int c1, int w, int out,
+                                          int kmin, int kmax)
+{
+    const T(*src)[MW] = ring->v[(c1 + 4) & (PRING - 1)];
+    double f1[NQ], fw[NQ];
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) f1[i] = (double)src[i][lane];
+    wall_values(a, blocks_of(a), f1, side, fw);
+    if (kmin == 0) {
+        T(*dst)[MW] = ring->v[(w + 4) & (PRING - 1)];
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) dst[i][lane] = (T)fw[i];
+    }
+    if (kmax == 1) {
+        T(*dst)[MW] = ring->v[(w + out + 4) & (PRING - 1)];
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) dst[i][lane] = (T)(2.0 * fw[i] - f1[i]);
+    }
+}
 
 // One wavefront's walk through its band in direction DIR (+1: increasing y).
 // The window W holds four rows of all 16 planes: for output row j walked in
@@ -404,6 +430,23 @@ struct Marcher {
         velocity(W[E], U[E], V[E], a);
     }
 
+    // ROLE_FIRST: row j of step n + 1 on a high wall side (k = 0: the wall
+    // node's row, 1: its first ghost row), refilled from the row below the
+    // wall instead of stepped; equilibrium ghost columns keep their value.
+    __device__ __forceinline__ void wall_row(int j, int k)
+    {
+        CArgs& a = args();
+        if (pass) {
+            T v[NQ];
+            load(v, j, a);
+            T(*dst)[MW] = ring->v[(j + 4) & (PRING - 1)];
+#pragma unroll
+            for (int i = 0; i < NQ; ++i) dst[i][lane] = v[i];
+        } else {
+            ring_wall(a, ring, lane, 3, a.ny - 2, a.ny - 1, 1, k, k);
+        }
+    }
+
     // Load the window of output row j in phase 0 (W[3] = row j - 2 DIR,
     // W[0] = j - DIR, W[1] = j, W[2] = j + DIR) and the carried face jumps.
     __device__ __forceinline__ void prime(int j)
@@ -546,6 +589,15 @@ __device__ __forceinline__ void pair_rows(M& m, int j, int n)
 // reading r(k + 2), which the first finished one iteration before.  A ring
 // slot is rewritten three iterations after it was last read at the
 // earliest (outflow ghost rows read the last interior row).
+//
+// Walls along y (DIR > 0 only): the second step needs the wall rows of step
+// n + 1 as the refill after a step leaves them.  On the high side the first
+// wavefront refills its last rows that reach the wall (at most two: the
+// wall node's row and its ghost, from row ny - 2) at their own iterations,
+// after its window is dead.  On the low side rows 0 and -1 are made before
+// row 1, so the second wavefront, idle until iteration 4, refills them at
+// iteration 3 from row 1 (made by iteration 2) while the first writes
+// r(1), which is row 2 or 3 and lands in another slot.
 template <int LIM, typename T, int DIR>
 __device__ __forceinline__ void pair_walk(int role, CArgs& a, const T* fin, T* fout, unsigned bytes, int x, int lane,
                                           int yb, int ye, PairRing<T>* ring)
@@ -559,21 +611,41 @@ __device__ __forceinline__ void pair_walk(int role, CArgs& a, const T* fin, T* f
         __builtin_amdgcn_s_setprio(MARCH2_PRIO_FIRST);
 #endif
         Marcher<LIM, T, DIR, ROLE_FIRST> m(&a, fin, fout, bytes, x, lane, ring);
+        // rows r(k) >= ny - 1 on a high wall side are refilled, not stepped
+        const int lead = (DIR > 0 && a.bc[3] == BC_WALL) ? max(0, ye + 3 - a.ny) : 0;
+        const int nn = H + 4 - lead;             // rows stepped: r(-2) .. r(nn - 3)
+        const int ns = min(nn, 4);
         int j = j0 - 2 * DIR;
         m.prime(j);
-        for (int t = 0; t < 4; ++t) {            // rows r(-2) .. r(1)
+        for (int t = 0; t < ns; ++t) {           // rows r(-2) .. r(1)
             m.template row<0>(j);
             j += DIR;
             m.advance();
             pair_sync();
         }
-        pair_sync();                             // iteration 4: the second loads its window
-        pair_rows(m, j, H);                      // iterations 5 .. H + 4: rows r(2) .. r(H + 1)
-        pair_sync();                             // iteration H + 5
+        int it = ns;
+        if (nn >= 4) {
+            pair_sync();                         // iteration 4: the second loads its window
+            pair_rows(m, j, nn - 4);             // iterations 5 .. nn: rows r(2) .. r(nn - 3)
+            it = nn + 1;
+        }
+        for (int k = nn - 2; k <= H + 1; ++k) {  // refilled rows, each at its own iteration
+            const int at = (k <= 1) ? k + 2 : k + 3;
+            for (; it < at; ++it) pair_sync();
+            m.wall_row(yb + k, yb + k - (a.ny - 1));
+            pair_sync();
+            ++it;
+        }
+        for (; it < H + 6; ++it) pair_sync();    // through iteration H + 5
     } else {
         Marcher<LIM, T, DIR, ROLE_SECOND> m(&a, fin, fout, bytes, x, lane, ring);
         int j = j0;
-        for (int t = 0; t < 4; ++t) pair_sync(); // iterations 0 .. 3
+        for (int t = 0; t < 3; ++t) pair_sync(); // iterations 0 .. 2
+        if (DIR > 0 && a.bc[2] == BC_WALL && yb <= 2) {
+            const bool pass = (x < 0 && a.bc[0] == BC_EQUIL) || (x >= a.nx && a.bc[1] == BC_EQUIL);
+            if (!pass) ring_wall(a, ring, lane, 2, 1, 0, -1, 0, (yb == 1) ? 1 : 0);
+        }
+        pair_sync();                             // iteration 3
         m.prime(j);                              // iteration 4
         pair_sync();
         pair_sync();                             // iteration 5
@@ -584,7 +656,8 @@ __device__ __forceinline__ void pair_walk(int role, CArgs& a, const T* fin, T* f
 // Two steps per pass: block b holds one pair, item (b mod 8) * per_xcd +
 // b / 8 (XCD-aware, as in k_march), numbered band after band, strip by
 // strip within a band; wavefront 0 takes the first step, wavefront 1 the
-// second.  Walls are not supported (their refill sits between two steps).
+// second.  Walls along y are refilled inside the pair (every band walks up);
+// walls along x are not supported.
 #ifndef MARCH2_MINW
 #define MARCH2_MINW 2            // wavefronts per SIMD the pair kernel must fit (register budget)
 #endif

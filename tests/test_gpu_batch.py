@@ -30,6 +30,7 @@ def lib():
 
 
 P, E, O = W.bc("periodic"), W.bc("equilibrium", 1.1, 0.05, -0.02, 0.9), W.bc("outflow")
+WL, WH = W.bc("wall", 1.0, 0.0, 0.0, 1.0), W.bc("wall", 1.0, 0.15, 0.0, 1.05)
 
 
 def mixed_cases(limiter="mc"):
@@ -172,16 +173,23 @@ def test_budgets_and_membership_changes(lib):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_two_step_rounds_match_one_step(lib, precision):
-    # slots that take two steps per launch (strips, no walls, >= 8 rows)
-    # next to ones that cannot (walls, short, tiles); odd and even budgets,
+    # slots that take two steps per launch (strips, no walls along x, >= 8
+    # rows) next to ones that cannot (short, tiles); odd and even budgets,
     # a restart and a class change mid-run, a slot joining late; the
     # 4096 x 1024 instance makes the two-step work fill the device twice
-    # over, which two-step rounds need (it is compared by its macros)
+    # over, which two-step rounds need (it is compared by its macros).
+    # Walls along y (refilled inside the pairs) with 32-row pair bands: the
+    # last band 1 row (the one before it ending two rows below the wall),
+    # 2 rows, a low wall only, a high wall only
     cases = mixed_cases() + [W.random_smooth(300, 150, seed=21, bcs=[E, O, P, P], jumps=True),
                              W.random_smooth(90, 64, seed=22, bcs=[O, O, O, O], jumps=True),
-                             W.random_smooth(4096, 1024, seed=24, bcs=[E, O, P, P], jumps=True)]
+                             W.random_smooth(4096, 1024, seed=24, bcs=[E, O, P, P], jumps=True),
+                             W.random_smooth(200, 35, seed=25, bcs=[P, P, WL, WH], jumps=True),
+                             W.random_smooth(150, 36, seed=26, bcs=[E, O, WL, WH], jumps=True),
+                             W.random_smooth(100, 67, seed=27, bcs=[O, O, WL, O], jumps=True),
+                             W.random_smooth(90, 40, seed=28, bcs=[E, E, E, WH], jumps=True)]
     cases = [dict(c, params=dict(c["params"], precision=precision)) for c in cases]
-    budgets = [7, 40, 33, -1, 40, 0, 21, 40, 39, 40, -1]
+    budgets = [7, 40, 33, -1, 40, 0, 21, 40, 39, 40, -1, 40, 31, -1, 38]
     late = W.random_smooth(120, 48, seed=23, bcs=[P, P, P, P], jumps=True)
     late = dict(late, params=dict(late["params"], precision=precision))
     out = {}
@@ -203,19 +211,19 @@ def test_two_step_rounds_match_one_step(lib, precision):
             out[k] = ([b.macros(s) if s == slots[10] else b.get_f(s) for s in slots + [s_late]],
                       [b.steps_done(s) for s in slots + [s_late]])
     assert out[1][1] == out[2][1]
-    assert out[2][1] == [7, 40, 33, 9, 40, 0, 21, 40, 39, 40, 44, 25]
+    assert out[2][1] == [7, 40, 33, 9, 40, 0, 21, 40, 39, 40, 44, 40, 31, 44, 38, 25]
     for a, c, case in zip(out[1][0], out[2][0], cases + [late]):
         if isinstance(a, tuple):
             assert all(np.array_equal(x, y) for x, y in zip(a, c)), case["name"]
         else:
             assert np.array_equal(a, c), case["name"]
     # and against one instance alone
-    for idx in (8, 9):
+    for idx in (8, 9, 11, 12, 13, 14):
         c = cases[idx]
         with lib.Solver(c["params"]) as single:
             single.steps_per_launch = 1
             single.init(c["rho"], c["ux"], c["uy"], c["T"])
-            single.step(budgets[idx])
+            single.step(out[2][1][idx])
             assert np.array_equal(single.get_f(), out[2][0][idx]), c["name"]
 
 

@@ -9,10 +9,13 @@ ghosts computed by translation, equilibrium ghosts passed through, outflow
 ghosts read at their source lane or row), grids narrower than a strip,
 ragged strips, one-row and few-row grids (a band reaching both edges),
 launches with many bands, both storage precisions and all four limiters.
-Walls are rejected for fusion.  The fused path is also compared with the
-oracle directly (every boundary kind, both precisions), and the other GPU
-tests run it wherever it is the default (large grids, e.g. the full
-4096 x 1024 shock-interface windows).
+Walls along y are refilled inside the pair (the wall rows of the first
+step's result, written into the ring of rows); cases cover them with every
+x boundary kind, one or both walls, and band layouts whose bands reach a
+wall within one or two rows.  Walls along x are rejected for fusion.  The
+fused path is also compared with the oracle directly (every boundary kind,
+both precisions), and the other GPU tests run it wherever it is the default
+(large grids, e.g. the full 4096 x 1024 shock-interface windows).
 """
 import numpy as np
 import pytest
@@ -35,6 +38,8 @@ def lib():
 P, O = W.bc("periodic"), W.bc("outflow")
 E1, E2 = W.bc("equilibrium", 1.1, 0.05, -0.02, 0.9), W.bc("equilibrium", 0.8, -0.1, 0.03, 1.2)
 AXES = {"P": (P, P), "E": (E1, E2), "O": (O, O), "EO": (E1, O), "OE": (O, E2)}
+WL, WH = W.bc("wall", 1.0, 0.0, 0.0, 1.0), W.bc("wall", 1.0, 0.15, 0.0, 1.05)
+YWALLS = {"WW": (WL, WH), "WO": (WL, O), "WE": (WL, E2), "OW": (O, WH), "EW": (E1, WH)}
 
 
 def state(lib, case, per_launch, nsteps):
@@ -94,16 +99,56 @@ def test_shock_interface_full_size(lib):
     check(lib, c, 6)
 
 
-def test_walls_are_not_fused(lib):
-    WL, WH = W.bc("wall", 1.0, 0.0, 0.0, 1.0), W.bc("wall", 1.0, 0.15, 0.0, 1.05)
-    c = W.random_smooth(64, 40, bcs=[P, P, WL, WH])
+@pytest.mark.parametrize("xa", ["P", "E", "O"])
+@pytest.mark.parametrize("yw", list(YWALLS))
+def test_walls_along_y(lib, xa, yw):
+    bcs = list(AXES[xa]) + list(YWALLS[yw])
+    c = W.random_smooth(131, 70, seed=8, bcs=bcs, jumps=True)
+    check(lib, c, 9)
+
+
+# Band layouts (1024 resident pairs): one-row bands, where every band near
+# a wall reaches it within one or two rows (3..7 rows); and taller bands
+# whose last band has 1 row (1000 x 297: 6-row bands, the one before it
+# ends two rows below the wall; 50 x 2001: 2-row bands), 2 rows
+# (1000 x 298), 4 rows (1000 x 300) or 14 rows (1500 x 700).
+@pytest.mark.parametrize("nx,ny", [(64, 3), (64, 4), (5, 5), (60, 6), (57, 7), (1000, 297), (1000, 298),
+                                   (1000, 300), (50, 2001), (1500, 700)])
+@pytest.mark.parametrize("xa", ["P", "E"])
+def test_wall_band_layouts(lib, nx, ny, xa):
+    bcs = list(AXES[xa]) + [WL, WH]
+    c = W.random_smooth(nx, ny, seed=nx + ny, bcs=bcs, jumps=nx > 4)
+    check(lib, c, 8)
+
+
+@pytest.mark.parametrize("limiter", ["mc", "minmod"])
+def test_walls_fp32(lib, limiter):
+    c = W.random_smooth(1000, 297, seed=9, bcs=[E1, O, WL, WH], limiter=limiter, precision="fp32", jumps=True)
+    check(lib, c, 7)
+
+
+def test_couette_fused(lib):
+    c = W.couette(pr=1.0, nx=130, ny=200)
+    check(lib, c, 50)
+
+
+def test_fusion_rules(lib):
+    c = W.random_smooth(64, 40, bcs=[WL, WH, P, P])
     with lib.Solver(c["params"]) as s:
-        assert s.steps_per_launch == 1
+        assert s.steps_per_launch == 1          # walls along x: never fused
         with pytest.raises(lib.MRTFDError):
             s.steps_per_launch = 2
         with pytest.raises(lib.MRTFDError):
             s.steps_per_launch = 3
         assert s.steps_per_launch == 1
+    c = W.random_smooth(64, 40, bcs=[P, P, WL, WH])
+    with lib.Solver(c["params"]) as s:
+        assert s.steps_per_launch == 1          # walls along y: fused on request
+        s.steps_per_launch = 2
+        assert s.steps_per_launch == 2
+    c = W.random_smooth(1024, 512, bcs=[P, P, WL, WH])
+    with lib.Solver(c["params"]) as s:
+        assert s.steps_per_launch == 2          # and by default on a large grid
     c = W.random_smooth(1024, 512)
     with lib.Solver(c["params"]) as s:
         assert s.steps_per_launch == 2          # FP64 on a large grid: fused by default
@@ -122,10 +167,14 @@ def test_walls_are_not_fused(lib):
         assert s.steps_per_launch == 2
 
 
-@pytest.mark.parametrize("axes", ["PP", "EO", "OE", "EP", "OO"])
+@pytest.mark.parametrize("axes", ["PP", "EO", "OE", "EP", "OO", "P-WW", "E-WO", "O-EW"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_fused_against_oracle(lib, orc, axes, precision):
-    bcs = list(AXES[axes[0]]) + list(AXES[axes[1]])
+    if "-" in axes:
+        xa, yw = axes.split("-")
+        bcs = list(AXES[xa]) + list(YWALLS[yw])
+    else:
+        bcs = list(AXES[axes[0]]) + list(AXES[axes[1]])
     c = W.random_smooth(150, 61, seed=5, bcs=bcs, precision=precision, jumps=True)
     n = 10
     print(f"[fused-oracle] 150x61 {axes} {precision} n={n}", flush=True)
