@@ -212,13 +212,13 @@ int mrtfd_batch_set_steps(mrtfd_batch_t b, int slot, long nsteps);
 int mrtfd_batch_step(mrtfd_batch_t b, long nsteps);
 
 /* Steps per launch of the batch's two-step rounds: with k = 2 (default),
- * slots in the strip class without walls along x and with at least 8 rows take two
- * steps per launch (the second step reading the first's rows from on-chip
- * memory) in rounds where every such slot has two steps left and their
- * work fills the device (a smaller batch is faster one step at a time);
- * other slots take two one-step launches in those rounds.  k = 1: one step per launch
- * for every slot.  Results are bitwise the same either way; MRTFD_EINVAL
- * for k other than 1 or 2. */
+ * slots in the strip class without walls along x and with at least 8 rows
+ * take two steps per launch (the second step reading the first's rows from
+ * on-chip memory) in rounds where their work fills the device (a smaller
+ * batch is faster one step at a time); other slots, and such slots with one
+ * step left, take one-step launches in those rounds.  k = 1: one step per
+ * launch for every slot.  Results are bitwise the same either way;
+ * MRTFD_EINVAL for k other than 1 or 2. */
 int mrtfd_batch_set_steps_per_launch(mrtfd_batch_t b, int k);
 int mrtfd_batch_get_steps_per_launch(mrtfd_batch_t b, int* k);
 int mrtfd_batch_step_timed(mrtfd_batch_t b, long nsteps, double* elapsed_ms);

@@ -13,10 +13,11 @@
 // Shape classes: the row-marching strips of mrtfd_march.h (60 output
 // columns x bands of up to 12 rows per wavefront), and LDS tiles of 256
 // threads: 32 x 8, 64 x 4, 128 x 2, and 256 x 1 rows for one-row instances.
-// Strip slots without walls along x and with at least 8 rows take two steps per
-// launch (k_march2_batch, bands of up to 32 rows) in two-step rounds, which
-// the batch runs while every such slot has two steps left; the other slots
-// then take two one-step launches.
+// Strip slots without walls along x and with at least 8 rows take two
+// steps per launch (k_march2_batch, bands of up to 32 rows) in two-step
+// rounds, which the batch runs while their work fills the device; the
+// other slots, and such slots with one step left, then take one-step
+// launches.
 // Each slot gets the class with the smallest estimated cost (work units x
 // cost per unit; a unit is a tile, or one row of a strip including the halo
 // rows of its bands); mrtfd_batch_autotune measures the cost per unit of
@@ -197,6 +198,25 @@ int upload_slot(mrtfd_batch_s* B, int k)
     return MRTFD_OK;
 }
 
+// Whether slot k takes two steps per launch in the next two-step round: a
+// pair slot with two steps left.  A pair slot with one step left takes a
+// one-step launch in that round instead (its clock, R, still advances by one).
+bool takes_pair(const mrtfd_batch_s* B, int k)
+{
+    return B->slot[k].pair && B->slot[k].stop - B->L >= 2;
+}
+
+// Whether slot k is in work list s (slots that still step).
+bool in_list(const mrtfd_batch_s* B, int k, int s)
+{
+    if (!B->used[k] || B->L >= B->slot[k].stop) return false;
+    const int cls = (s == LIST_PAIR || s == LIST_SINGLE) ? MARCH : s;
+    if (B->shape[k] != cls) return false;
+    if (s == LIST_PAIR) return takes_pair(B, k);
+    if (s == LIST_SINGLE) return !takes_pair(B, k);
+    return true;
+}
+
 // Rebuild the work lists over slots that still step.
 int rebuild_lists(mrtfd_batch_s* B)
 {
@@ -207,11 +227,7 @@ int rebuild_lists(mrtfd_batch_s* B)
         int* pre = host.data() + s * (B->capacity + 1);
         int* lst = host.data() + NLIST * (B->capacity + 1) + s * B->capacity;
         for (int k = 0; k < B->capacity; ++k) {
-            if (!B->used[k] || B->L >= B->slot[k].stop) continue;
-            const int cls = (s == LIST_PAIR || s == LIST_SINGLE) ? MARCH : s;
-            if (B->shape[k] != cls) continue;
-            if (s == LIST_PAIR && !B->slot[k].pair) continue;
-            if (s == LIST_SINGLE && B->slot[k].pair) continue;
+            if (!in_list(B, k, s)) continue;
             pre[n] = acc;
             lst[n] = k;
             acc += (int)items_of(B->slot[k].a, s);
@@ -221,11 +237,11 @@ int rebuild_lists(mrtfd_batch_s* B)
         B->nlist[s] = n;
         if (s == LIST_PAIR) B->pair_items = acc;
     }
-    // slots with walls: the pair slots, then the others
+    // slots with walls: those that take two steps per launch, then the others
     int* wl = host.data() + NLIST * (B->capacity + 1) + NLIST * B->capacity;
     for (int pass = 1; pass >= 0; --pass) {
         for (int k = 0; k < B->capacity; ++k) {
-            if (!B->used[k] || B->L >= B->slot[k].stop || B->slot[k].pair != pass) continue;
+            if (!B->used[k] || B->L >= B->slot[k].stop || (int)takes_pair(B, k) != pass) continue;
             const mrtfd_params& p = B->prm[k];
             bool walls = false;
             for (int q = 0; q < 4; ++q) walls |= (p.bc[q].kind == BC_WALL);
@@ -284,13 +300,8 @@ int launch_lists(mrtfd_batch_s* B, const int* lists, int nl, long L, int walls)
         const int s = lists[q];
         if (!B->nlist[s]) continue;
         long items = 0;
-        for (int k = 0; k < B->capacity; ++k) {
-            if (!B->used[k] || B->L >= B->slot[k].stop) continue;
-            const int cls = (s == LIST_PAIR || s == LIST_SINGLE) ? MARCH : s;
-            if (B->shape[k] != cls || (s == LIST_PAIR && !B->slot[k].pair) || (s == LIST_SINGLE && B->slot[k].pair))
-                continue;
-            items += items_of(B->slot[k].a, s);
-        }
+        for (int k = 0; k < B->capacity; ++k)
+            if (in_list(B, k, s)) items += items_of(B->slot[k].a, s);
         int rc = 0;
         switch (B->limiter) {
         case 0: rc = launch_list<0, T>(B, s, items, L); break;
@@ -310,9 +321,9 @@ int launch_lists(mrtfd_batch_s* B, const int* lists, int nl, long L, int walls)
     return MRTFD_OK;
 }
 
-// Whether the next round can take two steps: some slot steps in pairs,
-// every such slot has two steps left, and the two-step launch fills the
-// device twice over.  (A pair band's 32 rows take 38 barrier-bound
+// Whether the next round can take two steps: some slot takes two steps per
+// launch (a pair slot with two steps left; the lists are current) and the
+// two-step launch fills the device twice over.  (A pair band's 32 rows take 38 barrier-bound
 // iterations for two steps, against about 26 rows walked by two one-step
 // launches of 12-row bands, so a batch too small to fill the device is
 // faster one step at a time: the lightly loaded served stream's median
@@ -327,15 +338,8 @@ int launch_lists(mrtfd_batch_s* B, const int* lists, int nl, long L, int walls)
 #endif
 bool two_step_round_ok(const mrtfd_batch_s* B)
 {
-    if (B->per_launch != 2 || B->pair_items < (long)MARCH2_BATCH_FILL * B->pair_blocks) return false;
-    bool any = false;
-    for (int k = 0; k < B->capacity; ++k) {
-        const BatchSlot& sl = B->slot[k];
-        if (!B->used[k] || !sl.pair || B->L >= sl.stop) continue;
-        if (sl.stop - B->L < 2) return false;
-        any = true;
-    }
-    return any;
+    return B->per_launch == 2 && B->nlist[LIST_PAIR] > 0 &&
+           B->pair_items >= (long)MARCH2_BATCH_FILL * B->pair_blocks;
 }
 
 // One round: one step of every stepping slot, or (two = true) two steps,
@@ -365,8 +369,9 @@ int launch_round_t(mrtfd_batch_s* B, bool two)
         B->L += 1;
     }
     B->R += 1;
-    // slots whose budget just ran out leave the work lists; pair slots
-    // keep the round at which they stopped
+    // slots whose budget just ran out leave the work lists (pair slots keep
+    // the round at which they stopped); pair slots left with one step move
+    // to the one-step list
     for (int k = 0; k < B->capacity; ++k) {
         if (!B->used[k]) continue;
         const long stop = B->slot[k].stop;
@@ -374,6 +379,7 @@ int launch_round_t(mrtfd_batch_s* B, bool two)
             B->dirty = true;
             if (B->slot[k].pair) B->rstop[k] = B->R;
         }
+        if (B->slot[k].pair && stop - B->L == 1) B->dirty = true;
     }
     return MRTFD_OK;
 }
