@@ -57,11 +57,16 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_march2_shock_interface_
 
 
 def kernel_hash() -> str:
+    """Hash of what builds and launches the single-instance step kernels (the
+    sources other than the batched entry points, and the build flags): the
+    stored traffic counters are reported only while it matches."""
     h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_1305_4736_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, name), "rb") as fh:
-            h.update(name.encode())
+    pkg = os.path.join(ROOT, "paper_1305_4736_amd")
+    csrc = os.path.join(pkg, "csrc")
+    files = [os.path.join(csrc, n) for n in sorted(os.listdir(csrc)) if n != "mrtfd_batch.hip"]
+    for path in files + [os.path.join(pkg, "build.py")]:
+        with open(path, "rb") as fh:
+            h.update(os.path.basename(path).encode())
             h.update(fh.read())
     return h.hexdigest()[:16]
 
