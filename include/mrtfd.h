@@ -117,8 +117,9 @@ int mrtfd_init(mrtfd_t h, const double* rho, const double* ux, const double* uy,
  * memory, so the state crosses HBM once per two steps; an odd remainder,
  * and handles set to one step per launch, take one launch per step (the
  * row-marching form for state buffers below 2 GiB, else the LDS-tile
- * form).  Each launch is followed by a small launch that refills NEE walls
- * if there are any.  Every form gives the same bits.
+ * form).  NEE walls along y are refilled by the row-marching kernels
+ * themselves; other walls (along x, or in the LDS-tile form) by a small
+ * launch after each step.  Every form gives the same bits.
  * Asynchronous on the handle's stream; non-finite or unphysical nodes are
  * flagged on the device and reported by mrtfd_sync. */
 int mrtfd_step(mrtfd_t h, long nsteps);

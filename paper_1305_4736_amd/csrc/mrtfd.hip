@@ -11,9 +11,11 @@
 // and y flux differences of its 16 populations (Sec. III flux and limiter
 // eqs.) and the new populations.  The march reads periodic and outflow
 // sides at their source nodes (the LDS-tile form for states of 2 GiB and
-// more writes those ghost images instead); walls, if any, are refilled by
-// a small kernel after each launch (and, inside a two-step launch, in its
-// ring of rows); equilibrium ghosts are constant and written once.
+// more writes those ghost images instead); NEE walls along y are refilled
+// by the march kernels themselves (by the wavefronts whose bands end at a
+// wall, and between the two steps of a two-step launch in its ring of
+// rows), other walls by a small kernel after the step; equilibrium ghosts
+// are constant and written once.
 #include <hip/hip_runtime.h>
 
 #include <new>
@@ -134,14 +136,17 @@ int ensure_staging(mrtfd_s* h, size_t bytes)
     return MRTFD_OK;
 }
 
-// Wall rows and their ghosts of the new state fout, from the rows next to
-// the walls (after a one- or two-step launch).
+// Wall columns or rows and their ghosts of the new state fout, from the
+// nodes next to the walls, after a launch that did not refill them: the
+// LDS-tile form, and walls along x (the march kernels refill walls along y
+// themselves).
 template <typename T>
-int refill_walls(mrtfd_s* h, T* fout)
+int refill_walls(mrtfd_s* h, T* fout, bool march)
 {
     const StepArgs& a = h->args;
     for (int axis = 0; axis < 2; ++axis) {
         if (a.bc[2 * axis] != BC_WALL && a.bc[2 * axis + 1] != BC_WALL) continue;
+        if (march && axis == 1) continue;
         const int n = 2 * ((axis == 0) ? a.ny : a.nx);
         hipLaunchKernelGGL((k_fill<T>), dim3((n + 127) / 128), dim3(128), 0, h->stream, fout, a, axis, 1);
         HIPCHK(hipGetLastError());
@@ -177,7 +182,7 @@ int launch_step_t(mrtfd_s* h)
             }
         }
         HIPCHK(hipGetLastError());
-        int rc = refill_walls<T>(h, fout);
+        int rc = refill_walls<T>(h, fout, march_fits<T>(a));
         if (rc) return rc;
     }
     h->cur = 1 - h->cur;
@@ -204,8 +209,7 @@ int launch_pair_t(mrtfd_s* h)
     default: hipLaunchKernelGGL((k_march2<3, T>), grid, block, 0, h->stream, fin, fout, h->args_dev); break;
     }
     HIPCHK(hipGetLastError());
-    int rc = refill_walls<T>(h, fout);
-    if (rc) return rc;
+    // (no walls along x; walls along y are refilled by the kernel)
     h->cur = 1 - h->cur;
     return MRTFD_OK;
 }

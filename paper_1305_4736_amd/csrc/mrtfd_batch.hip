@@ -97,7 +97,6 @@ struct mrtfd_batch_s {
     int* d_flags;
     int* d_lists;                       // NLIST x (capacity + 1) prefixes, then NLIST x capacity slot lists, then walls
     int nlist[NLIST], nwall;
-    int nwall_pair;                     // the wall list holds the pair slots' first
     bool dirty;
     long L;                             // steps taken by the batch
     long R;                             // rounds (one or two steps each)
@@ -237,17 +236,16 @@ int rebuild_lists(mrtfd_batch_s* B)
         B->nlist[s] = n;
         if (s == LIST_PAIR) B->pair_items = acc;
     }
-    // slots with walls: those that take two steps per launch, then the others
+    // slots whose walls a refill launch rewrites after each step: walls in
+    // the tile classes, and walls along x (the strip kernels refill walls
+    // along y themselves; strip slots with walls along x never take pairs)
     int* wl = host.data() + NLIST * (B->capacity + 1) + NLIST * B->capacity;
-    for (int pass = 1; pass >= 0; --pass) {
-        for (int k = 0; k < B->capacity; ++k) {
-            if (!B->used[k] || B->L >= B->slot[k].stop || (int)takes_pair(B, k) != pass) continue;
-            const mrtfd_params& p = B->prm[k];
-            bool walls = false;
-            for (int q = 0; q < 4; ++q) walls |= (p.bc[q].kind == BC_WALL);
-            if (walls) wl[B->nwall++] = k;
-        }
-        if (pass == 1) B->nwall_pair = B->nwall;
+    for (int k = 0; k < B->capacity; ++k) {
+        if (!B->used[k] || B->L >= B->slot[k].stop) continue;
+        const mrtfd_params& p = B->prm[k];
+        const bool wx = p.bc[0].kind == BC_WALL || p.bc[1].kind == BC_WALL;
+        const bool wy = p.bc[2].kind == BC_WALL || p.bc[3].kind == BC_WALL;
+        if (wx || (wy && B->shape[k] != MARCH)) wl[B->nwall++] = k;
     }
     HIPCHK(hipMemcpyAsync(B->d_lists, host.data(), host.size() * sizeof(int), hipMemcpyHostToDevice, B->stream));
     B->dirty = false;
@@ -290,11 +288,10 @@ int launch_list(mrtfd_batch_s* B, int s, long items, long L)
     return MRTFD_OK;
 }
 
-// Wall refill after a launch: the pair slots' walls, the others', or all.
-enum { WALLS_PAIR, WALLS_SINGLE, WALLS_ALL };
-
+// One-step launches over work lists `lists` at step counter L, then the
+// refill launch for the walls the kernels leave (refill = true).
 template <typename T>
-int launch_lists(mrtfd_batch_s* B, const int* lists, int nl, long L, int walls)
+int launch_lists(mrtfd_batch_s* B, const int* lists, int nl, long L, bool refill)
 {
     for (int q = 0; q < nl; ++q) {
         const int s = lists[q];
@@ -311,11 +308,9 @@ int launch_lists(mrtfd_batch_s* B, const int* lists, int nl, long L, int walls)
         }
         if (rc) return rc;
     }
-    const int w0 = (walls == WALLS_SINGLE) ? B->nwall_pair : 0;
-    const int w1 = (walls == WALLS_PAIR) ? B->nwall_pair : B->nwall;
-    if (w1 > w0) {
-        hipLaunchKernelGGL((k_wall_batch<T>), dim3(w1 - w0), dim3(256), 0, B->stream, B->d_slot, wall_dev(B) + w0,
-                           L, B->R);
+    if (refill && B->nwall) {
+        hipLaunchKernelGGL((k_wall_batch<T>), dim3(B->nwall), dim3(256), 0, B->stream, B->d_slot, wall_dev(B), L,
+                           B->R);
         HIPCHK(hipGetLastError());
     }
     return MRTFD_OK;
@@ -354,17 +349,17 @@ int launch_round_t(mrtfd_batch_s* B, bool two)
     const long L0 = B->L;
     if (two) {
         const int pairs[] = {LIST_PAIR};
-        int rc = launch_lists<T>(B, pairs, 1, L0, WALLS_PAIR);
+        int rc = launch_lists<T>(B, pairs, 1, L0, false);
         if (rc) return rc;
         const int others[] = {0, 1, 2, 3, LIST_SINGLE};
         for (int h = 0; h < 2; ++h) {
-            rc = launch_lists<T>(B, others, 5, L0 + h, WALLS_SINGLE);
+            rc = launch_lists<T>(B, others, 5, L0 + h, true);
             if (rc) return rc;
         }
         B->L += 2;
     } else {
         const int all[] = {0, 1, 2, 3, MARCH};
-        int rc = launch_lists<T>(B, all, 5, L0, WALLS_ALL);
+        int rc = launch_lists<T>(B, all, 5, L0, true);
         if (rc) return rc;
         B->L += 1;
     }

@@ -112,6 +112,9 @@ __device__ __forceinline__ CBlocks& blocks_of(CArgs& a) { return *(CBlocks*)a.Bp
 constexpr int BUF_WORD3 = 0x00020000;   // raw 32-bit data format (gfx9 family)
 constexpr unsigned NO_STORE = 0x80000000u;
 typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+// s_waitcnt immediate (gfx9 family) that waits for every vector memory
+// operation of the wavefront: vmcnt 0, expcnt and lgkmcnt at their maxima.
+constexpr int MRTFD_WAIT_VM0 = 0x0F70;
 
 __device__ __forceinline__ double buf_load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, double*)
 {
@@ -447,6 +450,44 @@ struct Marcher {
         }
     }
 
+    // NEE walls along y of the new state, refilled by the wavefront whose
+    // band ends at a wall, after its walk: the row next to the wall is read
+    // back from the output (this lane wrote it) and the wall node's row and
+    // its two ghost rows are written by the same arithmetic as the refill
+    // launch, on the output lanes.  Walls along x are refilled by a launch.
+    __device__ __forceinline__ void refill_walls(int yb, int ye)
+    {
+        CArgs& a = args();
+        if (a.bc[0] == BC_WALL || a.bc[1] == BC_WALL) return;
+        const bool lo = a.bc[2] == BC_WALL && yb == a.y0;
+        const bool hi = a.bc[3] == BC_WALL && ye == a.y1;
+        if ((!lo && !hi) || vout == NO_STORE) return;
+        // this lane's stores of the walk are complete before the row is read
+        __builtin_amdgcn_s_waitcnt(MRTFD_WAIT_VM0);
+        if (lo) wall_rows(a, 2, a.y0, a.y0 - 1, -1);
+        if (hi) wall_rows(a, 3, a.y1 - 1, a.y1, 1);
+    }
+
+    // Wall node row cw and its ghost rows cw + out, cw + 2 out from output
+    // row c1, on this lane's column.
+    __device__ __forceinline__ void wall_rows(CArgs& a, int side, int c1, int cw, int out)
+    {
+        const unsigned pb = (unsigned)(a.plane * (long)sizeof(T));
+        const unsigned b1 = (unsigned)((a.org - 2 + (long)c1 * a.pitch) * (long)sizeof(T));
+        const unsigned b0 = (unsigned)((a.org - 2 + (long)cw * a.pitch) * (long)sizeof(T));
+        const unsigned step = (unsigned)((long)out * a.pitch * (long)sizeof(T));
+        double f1[NQ], fw[NQ];
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) f1[i] = (double)buf_load(rout, vout, b1 + (unsigned)i * pb, (T*)nullptr);
+        wall_values(a, blocks_of(a), f1, side, fw);
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) {
+            buf_store((T)fw[i], rout, vout, b0 + (unsigned)i * pb);
+            buf_store((T)(2.0 * fw[i] - f1[i]), rout, vout, b0 + step + (unsigned)i * pb);
+            buf_store((T)(3.0 * fw[i] - 2.0 * f1[i]), rout, vout, b0 + 2 * step + (unsigned)i * pb);
+        }
+    }
+
     // Load the window of output row j in phase 0 (W[3] = row j - 2 DIR,
     // W[0] = j - DIR, W[1] = j, W[2] = j + DIR) and the carried face jumps.
     __device__ __forceinline__ void prime(int j)
@@ -524,9 +565,11 @@ __global__ void __launch_bounds__(MW * MWPB, march_min_waves<T>()) k_march(const
     if (MARCH_ALTERNATE && (band & 1)) {
         Marcher<LIM, T, -1> mr(&a, fin, fout, bytes, x, out);
         mr.walk(yb, ye);
+        mr.refill_walls(yb, ye);
     } else {
         Marcher<LIM, T, 1> mr(&a, fin, fout, bytes, x, out);
         mr.walk(yb, ye);
+        mr.refill_walls(yb, ye);
     }
 }
 
@@ -650,6 +693,7 @@ __device__ __forceinline__ void pair_walk(int role, CArgs& a, const T* fin, T* f
         pair_sync();
         pair_sync();                             // iteration 5
         pair_rows(m, j, H);                      // iterations 6 .. H + 5: rows r(0) .. r(H - 1)
+        m.refill_walls(yb, ye);
     }
 }
 
@@ -800,9 +844,11 @@ __global__ void __launch_bounds__(MW * MWPB) k_march_batch(const BatchSlot* __re
         if (MARCH_ALTERNATE && (band & 1)) {
             Marcher<LIM, T, -1> mr(&a, fin, fout, bytes, x, out);
             mr.walk(yb, ye);
+            mr.refill_walls(yb, ye);
         } else {
             Marcher<LIM, T, 1> mr(&a, fin, fout, bytes, x, out);
             mr.walk(yb, ye);
+            mr.refill_walls(yb, ye);
         }
     }
 }

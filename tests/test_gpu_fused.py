@@ -12,7 +12,9 @@ launches with many bands, both storage precisions and all four limiters.
 Walls along y are refilled inside the pair (the wall rows of the first
 step's result, written into the ring of rows); cases cover them with every
 x boundary kind, one or both walls, and band layouts whose bands reach a
-wall within one or two rows.  Walls along x are rejected for fusion.  The
+wall within one or two rows.  The march kernels also refill the walls of
+their own output (along y), where the tile form launches a refill kernel;
+all forms agree bitwise.  Walls along x are rejected for fusion.  The
 fused path is also compared with the oracle directly (every boundary kind,
 both precisions), and the other GPU tests run it wherever it is the default
 (large grids, e.g. the full 4096 x 1024 shock-interface windows).
@@ -130,6 +132,33 @@ def test_walls_fp32(lib, limiter):
 def test_couette_fused(lib):
     c = W.couette(pr=1.0, nx=130, ny=200)
     check(lib, c, 50)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_wall_refill_forms_agree(lib, precision):
+    # walls along y are refilled by the march kernels themselves (one or two
+    # steps per launch, batched strips); the tile form and walls along x keep
+    # the refill launch: all give the same bits
+    cases = [W.random_smooth(131, 70, seed=31, bcs=[P, P, WL, WH], precision=precision, jumps=True),
+             W.random_smooth(90, 41, seed=32, bcs=[E1, O, WL, O], precision=precision, jumps=True),
+             W.random_smooth(77, 35, seed=33, bcs=[O, O, E1, WH], precision=precision, jumps=True),
+             W.couette(pr=1.0, nx=64, ny=50, precision=precision),
+             W.random_smooth(60, 40, seed=34, bcs=[WL, WH, P, P], precision=precision, jumps=True)]
+    n = 9
+    for c in cases:
+        xwalls = c["params"]["bc"][0]["kind"] == "wall"
+        print(f"[refill-forms] {c['name']} {precision} x walls {xwalls}", flush=True)
+        ref, _ = state(lib, c, 1, n)
+        assert np.all(np.isfinite(ref))
+        got = {} if xwalls else {"two steps per launch": state(lib, c, 2, n)[0]}
+        for shape in ("strips", "tile32x8", "tile64x4"):
+            with lib.Batch(2, precision=precision) as b:
+                slot = b.add(c["params"], c["rho"], c["ux"], c["uy"], c["T"], nsteps=n)
+                b.set_shape(slot, shape)
+                b.step(n)
+                got["batch " + shape] = b.get_f(slot)
+        for form, f in got.items():
+            assert np.array_equal(ref, f), (c["name"], form)
 
 
 def test_fusion_rules(lib):
