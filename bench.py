@@ -56,18 +56,49 @@ METRIC = "node-updates/s (D2V16 MRT-FD) + % HBM peak; p50/p99 served-solve laten
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_march2_shock_interface_4096x1024.json")
 
 
+def code_tokens(text: str, line_comment: str) -> str:
+    """The text without comments and with whitespace runs collapsed (string
+    literals kept whole), so that editing a comment does not change a hash."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if c in "\"'":
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif text.startswith(line_comment, i):
+            while i < n and text[i] != "\n":
+                i += 1
+        elif line_comment == "//" and text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+        elif c.isspace():
+            while i < n and text[i].isspace():
+                i += 1
+            if out and out[-1] != " ":
+                out.append(" ")
+        else:
+            out.append(c)
+            i += 1
+    return "".join(out).strip()
+
+
 def kernel_hash() -> str:
-    """Hash of what builds and launches the single-instance step kernels (the
-    sources other than the batched entry points, and the build flags): the
-    stored traffic counters are reported only while it matches."""
+    """Hash of the code that builds and launches the single-instance step
+    kernels (the sources other than the batched entry points, and the build
+    flags; comments and whitespace aside): the stored traffic counters are
+    reported only while it matches."""
     h = hashlib.sha256()
     pkg = os.path.join(ROOT, "paper_1305_4736_amd")
     csrc = os.path.join(pkg, "csrc")
     files = [os.path.join(csrc, n) for n in sorted(os.listdir(csrc)) if n != "mrtfd_batch.hip"]
     for path in files + [os.path.join(pkg, "build.py")]:
-        with open(path, "rb") as fh:
-            h.update(os.path.basename(path).encode())
-            h.update(fh.read())
+        with open(path, encoding="utf-8") as fh:
+            text = fh.read()
+        h.update(os.path.basename(path).encode())
+        h.update(code_tokens(text, "#" if path.endswith(".py") else "//").encode())
     return h.hexdigest()[:16]
 
 

@@ -401,7 +401,8 @@ __device__ void fill_line(T* __restrict__ f, const StepArgs& a, int axis, int t,
 }
 
 // Ghost fill of one axis (x-sides over rows, then y-sides over columns: two
-// launches); used after init and set_f, and for walls after each step.
+// launches); used after init and set_f, and after each step for the walls
+// the step kernel leaves (walls along x, and the LDS-tile form's).
 template <typename T>
 __global__ void k_fill(T* __restrict__ f, StepArgs a, int axis, int walls_only)
 {

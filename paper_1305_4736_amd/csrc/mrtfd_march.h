@@ -15,9 +15,10 @@
 //
 // Periodic and outflow sides are read at their source nodes (a column is
 // remapped once per lane, a row once per row), so this kernel writes no
-// ghost images; equilibrium ghosts are constant and NEE walls are refilled
-// by a separate launch after the step (and between the two steps of a pair
-// in its ring, for walls along y).
+// ghost images; equilibrium ghosts are constant.  NEE walls along y are
+// refilled by the wavefronts whose bands end at a wall, after their walk
+// (and between the two steps of a pair, in its ring); walls along x by a
+// separate launch after the step.
 //
 // Two steps per pass (k_march2): a block holds two wavefronts on the same
 // strip and band.  The first takes step n -> n+1 from HBM and leaves each
