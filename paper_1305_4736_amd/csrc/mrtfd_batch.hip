@@ -318,18 +318,19 @@ int launch_lists(mrtfd_batch_s* B, const int* lists, int nl, long L, bool refill
 
 // Whether the next round can take two steps: some slot takes two steps per
 // launch (a pair slot with two steps left; the lists are current) and the
-// two-step launch fills the device twice over.  (A pair band's 32 rows take 38 barrier-bound
-// iterations for two steps, against about 26 rows walked by two one-step
-// launches of 12-row bands, so a batch too small to fill the device is
-// faster one step at a time: the lightly loaded served stream's median
-// latency rose from 0.69 s to 1.10 s with pairs regardless.)
+// two-step launch fills the device.  (A pair band's 32 rows take 38
+// barrier-bound iterations for two steps, against about 26 rows walked by
+// two one-step launches of 12-row bands, so a batch far too small to fill
+// the device is faster one step at a time.)
 // Two-step work items a two-step round needs, in multiples of the resident
-// pairs (measured on the served stream at 15 requests/s: median / 99th
-// percentile latency 0.80 / 2.52 s with 1, 0.75 / 2.16 s with 2, 0.72 /
-// 2.16 s with 4, against 0.69 / 2.12 s without two-step rounds; the
-// overloaded stream gains 22 % throughput with any of them).
+// pairs.  Measured on the served stream at 15 requests/s, median / 99th
+// percentile latency (two runs each): 0.264 / 0.86 s with 1, 0.28-0.31 /
+// 0.93-0.96 s with 2, 0.28-0.29 / 0.96-0.98 s with 4, 0.336 / 0.76 s with
+// 0 (two-step rounds whenever a slot takes pairs), 0.29 / 0.98 s without
+// two-step rounds; the overloaded stream achieves 2.7-2.8e10 node-updates/s
+// with any of them and 1.76e10 without.
 #ifndef MARCH2_BATCH_FILL
-#define MARCH2_BATCH_FILL 2
+#define MARCH2_BATCH_FILL 1
 #endif
 bool two_step_round_ok(const mrtfd_batch_s* B)
 {
