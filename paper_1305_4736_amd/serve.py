@@ -8,7 +8,9 @@ storage precision) arrive over time.  The loop
     in the free HBM left after a reserve, under an optional cap on resident
     bytes;
   * keeps every admitted request's state resident as a slot of one of two
-    batches (FP32 storage, FP64), each slot with its own step budget;
+    batches (FP32 storage, FP64), each slot with its own step budget; by
+    default each batch has a stream of its own, so the two overlap on the
+    device;
   * every tick, advances both batches by `steps_per_tick` launches: all
     resident requests progress together, requests that arrived during the
     previous tick join as soon as they are admitted, and a request that uses
@@ -23,6 +25,7 @@ node-updates per second.
 from __future__ import annotations
 
 import collections
+import contextlib
 import time
 
 import numpy as np
@@ -39,12 +42,18 @@ class Server:
 
     def __init__(self, capacity=2048, steps_per_tick=50, reserve_bytes=8 << 30, max_resident_bytes=None,
                  limiter="mc", stream=None, keep_results=False, batch_factory=None, memory=None,
-                 materialize=None):
+                 materialize=None, overlap_nodes=1 << 25):
+        self.streams = None
         if batch_factory is None:
             import torch
             device = torch.device("cuda", torch.cuda.current_device())
-            self.stream = stream if stream is not None else torch.cuda.current_stream()
-            batch_factory = lambda cap, prec, lim: mrtfd.Batch(cap, precision=prec, limiter=lim, stream=self.stream)
+            if stream is not None:
+                self.streams = {"fp32": stream, "fp64": stream}
+            else:
+                # default priority, like every stream here
+                self.streams = {"fp32": torch.cuda.current_stream(), "fp64": torch.cuda.Stream(device=device)}
+            batch_factory = lambda cap, prec, lim: mrtfd.Batch(cap, precision=prec, limiter=lim,
+                                                              stream=self.streams[prec])
             if materialize is None:
                 materialize = lambda spec: W.materialize(spec, torch, device=device)
         self.materialize = materialize if materialize is not None else W.materialize
@@ -55,6 +64,19 @@ class Server:
         self.reserve = int(reserve_bytes)
         self.cap_bytes = max_resident_bytes
         self.keep_results = keep_results
+        # the two batches overlap on the device while either has fewer active
+        # nodes than this; two heavy batches take turns (each one's persistent
+        # launches are sized to fill the device, and sharing it cost 10 % of
+        # the overloaded stream's throughput)
+        self.overlap_nodes = int(overlap_nodes)
+
+    def _on(self, precision):
+        """Context in which a request's device fields are made: its batch's
+        stream, which then reads them in order."""
+        if self.streams is None:
+            return contextlib.nullcontext()
+        import torch
+        return torch.cuda.stream(self.streams[precision])
 
     def close(self):
         for b in self.batches.values():
@@ -106,7 +128,8 @@ class Server:
                         keep.append(i)
                         continue
                     b = self.batches[p["precision"]]
-                    slot = b.add(p, *self.materialize(spec), nsteps=spec["nsteps"])
+                    with self._on(p["precision"]):
+                        slot = b.add(p, *self.materialize(spec), nsteps=spec["nsteps"])
                     active[(p["precision"], slot)] = {"i": i, "t": t_arr if realtime else 0.0, "fp": fp,
                                                       "nodes": p["nx"] * p["ny"], "steps": spec["nsteps"]}
                     resident += fp
@@ -124,9 +147,13 @@ class Server:
                     time.sleep(max(0.0, min(reqs[nxt][0] - (time.perf_counter() - t0), 0.002)))
                 continue
             # one tick: every resident request advances (up to its budget)
-            for prec, b in self.batches.items():
-                if any(k[0] == prec for k in active):
-                    b.step(self.k)
+            nodes = {p: sum(r["nodes"] for k, r in active.items() if k[0] == p) for p in self.batches}
+            busy = [p for p in self.batches if nodes[p] > 0]
+            turns = self.streams is not None and len(busy) == 2 and min(nodes.values()) >= self.overlap_nodes
+            for i, prec in enumerate(busy):
+                if turns and i > 0:
+                    self.streams[prec].wait_stream(self.streams[busy[i - 1]])
+                self.batches[prec].step(self.k)
             for b in self.batches.values():
                 b.sync()
             ticks += 1
