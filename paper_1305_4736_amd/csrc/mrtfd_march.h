@@ -661,7 +661,7 @@ __device__ __forceinline__ void pair_walk(int role, CArgs& a, const T* fin, T* f
         const int ns = min(nn, 4);
         int j = j0 - 2 * DIR;
         m.prime(j);
-        for (int t = 0; t < ns; ++t) {           // rows r(-2) .. r(1)
+        for (int t = 0; t < ns; ++t) {           // rows r(-2) .. r(ns - 3), iterations 0 .. ns - 1
             m.template row<0>(j);
             j += DIR;
             m.advance();
@@ -673,7 +673,9 @@ __device__ __forceinline__ void pair_walk(int role, CArgs& a, const T* fin, T* f
             pair_rows(m, j, nn - 4);             // iterations 5 .. nn: rows r(2) .. r(nn - 3)
             it = nn + 1;
         }
-        for (int k = nn - 2; k <= H + 1; ++k) {  // refilled rows, each at its own iteration
+        // refilled rows (only with lead > 0, so DIR > 0 and r(k) = yb + k),
+        // each at its own iteration
+        for (int k = nn - 2; k <= H + 1; ++k) {
             const int at = (k <= 1) ? k + 2 : k + 3;
             for (; it < at; ++it) pair_sync();
             m.wall_row(yb + k, yb + k - (a.ny - 1));
