@@ -28,6 +28,15 @@
   the exact solution, and the paper's statements about Delta* on the centre
   line.
 
+* Sec. IV-C, thermal Couette flow on the 4 x 200 grid (gamma = 1.4, walls on
+  the first and last rows, the upper one moving at u_x = 0.2) for Pr = 0.5,
+  1 and 2, from rest to steady state (largest change of u_x, u_y, T over one
+  step below 1e-10), against the analytic profiles u = u_0 y and the
+  viscous-heating bump of T, and the bump's growth with Pr (analytic factor
+  4 from Pr = 0.5 to 2).  The method's own error at these rates is O(dy s_5)
+  in the bump (measured +13 %, +1.4 % and -5.1 % for Pr = 0.5, 1, 2; 1e-4 and
+  below in u); the bounds below leave room above those.
+
 The paper leaves the tube lengths open: L = 1 for the discontinuity, L = 3 for
 the Lax tube (the waves would stay inside up to the paper's t = 0.45).
 """
@@ -184,3 +193,37 @@ def test_heavy_light_noneq_characteristics(lib, orc):
     # Delta*_5, _7, _11 stay small (_7 and _11 vanish in a flow uniform in y)
     assert np.abs(ds[4]).max() < 0.1 * np.abs(ds[5]).max()
     assert np.abs(ds[6]).max() < 1e-10 and np.abs(ds[10]).max() < 1e-10
+
+
+def test_couette_steady_state_vs_analytic(lib):
+    ny = 200
+    y = np.arange(ny) / (ny - 1)
+    bumps = {}
+    for pr in (0.5, 1.0, 2.0):
+        c = W.couette(pr=pr, gamma=1.4)
+        with lib.Solver(c["params"]) as s:
+            s.init(c["rho"], c["ux"], c["uy"], c["T"])
+            n, chunk, res = 0, 5000, np.inf
+            while res >= 1e-10:
+                assert n < 400_000, f"Pr {pr}: no steady state after {n} steps (change {res:.2e})"
+                s.step(chunk - 1)
+                prev = s.macros()
+                s.step(1)
+                s.sync()
+                cur = s.macros()
+                n += chunk
+                res = max(np.abs(cur[q] - prev[q]).max() for q in (1, 2, 3))
+        rho, ux, uy, T = cur
+        ua, Ta = W.couette_analytic(y, pr, 1.4)
+        du = np.abs(ux - ua[:, None]).max() / 0.2
+        bumps[pr] = T[ny // 2].mean() - 1.0
+        rel = bumps[pr] / (Ta[ny // 2] - 1.0) - 1.0
+        print(f"[couette] Pr {pr}: {n} steps, max|u - u_a| / u_0 {du:.2e}, max|u_y| {np.abs(uy).max():.1e}, "
+              f"T bump {bumps[pr]:.4e} ({rel:+.3f} against analytic)", flush=True)
+        assert du < 2e-4
+        assert np.abs(uy).max() < 1e-4
+        assert abs(rel) < 0.2
+        # uniform along x (periodic)
+        assert np.abs(T - T[:, :1]).max() < 1e-12 and np.abs(ux - ux[:, :1]).max() < 1e-12
+    ratio = bumps[2.0] / bumps[0.5]
+    assert 3.0 < ratio < 4.6, ratio
