@@ -107,6 +107,10 @@ struct mrtfd_batch_s {
     double* staging;
     size_t staging_bytes;
     hipEvent_t ev0, ev1;
+    // a second stream (default priority) for the one-step launches of a
+    // two-step round, which overlap the pair launch (they step other slots)
+    hipStream_t side;
+    hipEvent_t fork, join;
     int max_blocks;
     int march_blocks;                   // resident blocks of the strip kernel on the device
     int pair_blocks;                    // resident blocks (pairs) of the two-step strip kernel
@@ -252,9 +256,9 @@ int rebuild_lists(mrtfd_batch_s* B)
     return MRTFD_OK;
 }
 
-// One launch over work list s at step counter L.
+// One launch over work list s at step counter L on stream st.
 template <int LIM, typename T>
-int launch_list(mrtfd_batch_s* B, int s, long items, long L)
+int launch_list(mrtfd_batch_s* B, int s, long items, long L, hipStream_t st)
 {
     const int* pre = prefix_dev(B, s);
     const int* lst = list_dev(B, s);
@@ -263,7 +267,7 @@ int launch_list(mrtfd_batch_s* B, int s, long items, long L)
         // persistent pairs, a multiple of 8 blocks for the XCD-aware numbering
         long blocks = std::min<long>(items, B->pair_blocks);
         blocks = (blocks + 7) / 8 * 8;
-        hipLaunchKernelGGL((k_march2_batch<LIM, T>), dim3((int)blocks), dim3(2 * MW), 0, B->stream, B->d_slot, pre,
+        hipLaunchKernelGGL((k_march2_batch<LIM, T>), dim3((int)blocks), dim3(2 * MW), 0, st, B->d_slot, pre,
                            lst, n, L, B->R);
         HIPCHK(hipGetLastError());
         return MRTFD_OK;
@@ -272,26 +276,26 @@ int launch_list(mrtfd_batch_s* B, int s, long items, long L)
         // persistent wavefronts; the XCD-aware numbering needs a multiple of 8 blocks
         long blocks = std::min<long>((items + MWPB - 1) / MWPB, B->march_blocks);
         blocks = (blocks + 7) / 8 * 8;
-        hipLaunchKernelGGL((k_march_batch<LIM, T>), dim3((int)blocks), dim3(MW * MWPB), 0, B->stream, B->d_slot, pre,
+        hipLaunchKernelGGL((k_march_batch<LIM, T>), dim3((int)blocks), dim3(MW * MWPB), 0, st, B->d_slot, pre,
                            lst, n, L, B->R);
         HIPCHK(hipGetLastError());
         return MRTFD_OK;
     }
     const int grid = (int)std::min<long>(items, B->max_blocks);
     switch (s) {
-    case 0: hipLaunchKernelGGL((k_step_batch<LIM, T, 32, 8, false>), dim3(grid), dim3(256), 0, B->stream, B->d_slot, pre, lst, n, L); break;
-    case 1: hipLaunchKernelGGL((k_step_batch<LIM, T, 64, 4, false>), dim3(grid), dim3(256), 0, B->stream, B->d_slot, pre, lst, n, L); break;
-    case 2: hipLaunchKernelGGL((k_step_batch<LIM, T, 128, 2, false>), dim3(grid), dim3(256), 0, B->stream, B->d_slot, pre, lst, n, L); break;
-    default: hipLaunchKernelGGL((k_step_batch<LIM, T, 256, 1, true>), dim3(grid), dim3(256), 0, B->stream, B->d_slot, pre, lst, n, L); break;
+    case 0: hipLaunchKernelGGL((k_step_batch<LIM, T, 32, 8, false>), dim3(grid), dim3(256), 0, st, B->d_slot, pre, lst, n, L); break;
+    case 1: hipLaunchKernelGGL((k_step_batch<LIM, T, 64, 4, false>), dim3(grid), dim3(256), 0, st, B->d_slot, pre, lst, n, L); break;
+    case 2: hipLaunchKernelGGL((k_step_batch<LIM, T, 128, 2, false>), dim3(grid), dim3(256), 0, st, B->d_slot, pre, lst, n, L); break;
+    default: hipLaunchKernelGGL((k_step_batch<LIM, T, 256, 1, true>), dim3(grid), dim3(256), 0, st, B->d_slot, pre, lst, n, L); break;
     }
     HIPCHK(hipGetLastError());
     return MRTFD_OK;
 }
 
-// One-step launches over work lists `lists` at step counter L, then the
+// Launches over work lists `lists` at step counter L on stream st, then the
 // refill launch for the walls the kernels leave (refill = true).
 template <typename T>
-int launch_lists(mrtfd_batch_s* B, const int* lists, int nl, long L, bool refill)
+int launch_lists(mrtfd_batch_s* B, const int* lists, int nl, long L, bool refill, hipStream_t st)
 {
     for (int q = 0; q < nl; ++q) {
         const int s = lists[q];
@@ -301,16 +305,15 @@ int launch_lists(mrtfd_batch_s* B, const int* lists, int nl, long L, bool refill
             if (in_list(B, k, s)) items += items_of(B->slot[k].a, s);
         int rc = 0;
         switch (B->limiter) {
-        case 0: rc = launch_list<0, T>(B, s, items, L); break;
-        case 1: rc = launch_list<1, T>(B, s, items, L); break;
-        case 2: rc = launch_list<2, T>(B, s, items, L); break;
-        default: rc = launch_list<3, T>(B, s, items, L); break;
+        case 0: rc = launch_list<0, T>(B, s, items, L, st); break;
+        case 1: rc = launch_list<1, T>(B, s, items, L, st); break;
+        case 2: rc = launch_list<2, T>(B, s, items, L, st); break;
+        default: rc = launch_list<3, T>(B, s, items, L, st); break;
         }
         if (rc) return rc;
     }
     if (refill && B->nwall) {
-        hipLaunchKernelGGL((k_wall_batch<T>), dim3(B->nwall), dim3(256), 0, B->stream, B->d_slot, wall_dev(B), L,
-                           B->R);
+        hipLaunchKernelGGL((k_wall_batch<T>), dim3(B->nwall), dim3(256), 0, st, B->d_slot, wall_dev(B), L, B->R);
         HIPCHK(hipGetLastError());
     }
     return MRTFD_OK;
@@ -349,18 +352,29 @@ int launch_round_t(mrtfd_batch_s* B, bool two)
     }
     const long L0 = B->L;
     if (two) {
-        const int pairs[] = {LIST_PAIR};
-        int rc = launch_lists<T>(B, pairs, 1, L0, false);
-        if (rc) return rc;
+        // the other slots' two one-step launches run on the side stream,
+        // beside the pair launch (forked after the list upload, joined back
+        // before anything else on the batch's stream)
         const int others[] = {0, 1, 2, 3, LIST_SINGLE};
-        for (int h = 0; h < 2; ++h) {
-            rc = launch_lists<T>(B, others, 5, L0 + h, true);
-            if (rc) return rc;
+        bool any = B->nwall > 0;
+        for (int s : others) any = any || B->nlist[s] > 0;
+        if (any) {
+            HIPCHK(hipEventRecord(B->fork, B->stream));
+            HIPCHK(hipStreamWaitEvent(B->side, B->fork, 0));
+            for (int h = 0; h < 2; ++h) {
+                int rc = launch_lists<T>(B, others, 5, L0 + h, true, B->side);
+                if (rc) return rc;
+            }
+            HIPCHK(hipEventRecord(B->join, B->side));
         }
+        const int pairs[] = {LIST_PAIR};
+        int rc = launch_lists<T>(B, pairs, 1, L0, false, B->stream);
+        if (rc) return rc;
+        if (any) HIPCHK(hipStreamWaitEvent(B->stream, B->join, 0));
         B->L += 2;
     } else {
         const int all[] = {0, 1, 2, 3, MARCH};
-        int rc = launch_lists<T>(B, all, 5, L0, true);
+        int rc = launch_lists<T>(B, all, 5, L0, true, B->stream);
         if (rc) return rc;
         B->L += 1;
     }
@@ -517,7 +531,10 @@ int mrtfd_batch_create(int capacity, int precision, int limiter, void* hip_strea
     if (hipMalloc(&B->d_slot, capacity * sizeof(BatchSlot)) != hipSuccess ||
         hipMalloc(&B->d_blocks, capacity * sizeof(Blocks)) != hipSuccess ||
         hipMalloc(&B->d_flags, capacity * sizeof(int)) != hipSuccess || hipMalloc(&B->d_lists, lists) != hipSuccess ||
-        hipEventCreate(&B->ev0) != hipSuccess || hipEventCreate(&B->ev1) != hipSuccess) {
+        hipEventCreate(&B->ev0) != hipSuccess || hipEventCreate(&B->ev1) != hipSuccess ||
+        hipStreamCreateWithFlags(&B->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&B->fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&B->join, hipEventDisableTiming) != hipSuccess) {
         (void)hipGetLastError();
         mrtfd_batch_destroy(B);
         return fail(MRTFD_ENOMEM, "batch set-up failed");
@@ -561,6 +578,12 @@ int mrtfd_batch_destroy(mrtfd_batch_t B)
     if (B->staging) (void)hipFree(B->staging);
     if (B->ev0) (void)hipEventDestroy(B->ev0);
     if (B->ev1) (void)hipEventDestroy(B->ev1);
+    if (B->side) {
+        (void)hipStreamSynchronize(B->side);
+        (void)hipStreamDestroy(B->side);
+    }
+    if (B->fork) (void)hipEventDestroy(B->fork);
+    if (B->join) (void)hipEventDestroy(B->join);
     delete B;
     return MRTFD_OK;
 }
