@@ -189,7 +189,10 @@ int mrtfd_constants(double eta0, double* M, double* Minv);
 typedef struct mrtfd_batch_s* mrtfd_batch_t;
 
 /* capacity slots (1 .. 65536); precision MRTFD_FP64 / MRTFD_FP32_STORAGE;
- * limiter MRTFD_LIM_*; hip_stream a hipStream_t (NULL = null stream). */
+ * limiter MRTFD_LIM_*; hip_stream a hipStream_t (NULL = null stream).  All
+ * work is ordered on hip_stream; the batch also owns one internal stream
+ * (default priority), forked from and joined back to hip_stream inside
+ * each step call. */
 int mrtfd_batch_create(int capacity, int precision, int limiter, void* hip_stream, mrtfd_batch_t* out);
 int mrtfd_batch_destroy(mrtfd_batch_t b);
 
