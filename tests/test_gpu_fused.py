@@ -134,6 +134,25 @@ def test_couette_fused(lib):
     check(lib, c, 50)
 
 
+def test_random_configurations(lib):
+    # a seeded sweep over grid sizes (1 to 300 columns, ragged strips), every
+    # boundary pair with walls along y, both precisions, all limiters and odd
+    # and even step counts
+    rng = np.random.default_rng(20260)
+    xkinds = ["P", "E", "O", "EO", "OE"]
+    ykinds = xkinds + list(YWALLS)
+    limiters = ["mc", "minmod", "lw", "upwind"]
+    for k in range(100):
+        nx = int(round(np.exp(rng.uniform(0.0, np.log(300)))))
+        ya = ykinds[rng.integers(len(ykinds))]
+        ny = int(rng.integers(3 if ya in YWALLS else 1, 120))
+        xa = xkinds[rng.integers(len(xkinds))]
+        bcs = list(AXES[xa]) + list(YWALLS[ya] if ya in YWALLS else AXES[ya])
+        c = W.random_smooth(nx, ny, seed=1000 + k, bcs=bcs, limiter=limiters[rng.integers(4)],
+                            precision=["fp64", "fp32"][rng.integers(2)], jumps=nx > 4)
+        check(lib, c, int(rng.integers(1, 12)))
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_wall_refill_forms_agree(lib, precision):
     # walls along y are refilled by the march kernels themselves (one or two
