@@ -284,3 +284,43 @@ def test_riemann_batch_subset_matches_oracle(lib, orc):
             mo = orc.macros(p64, fo)
             gamma = (c["params"]["b"] + 2.0) / c["params"]["b"]
             assert_parity(b.macros(s), mo, TOL["fp32"], gamma, f"{c['name']} {c['params']['nx']}x{c['params']['ny']}")
+
+
+def test_random_batch_matches_instances_alone(lib):
+    # random instances (walls along y among them) with random budgets, odd
+    # and even, stepped in uneven calls, a restart on the way; a 4096 x 1024
+    # instance (2368 pair items of 32 rows x 56 columns) keeps the pair work
+    # above the device's 1024 resident pairs, so two-step rounds run, and
+    # slots with one step left step inside them.
+    # Every slot ends bitwise equal to its instance run alone, one step per
+    # launch.
+    rng = np.random.default_rng(777)
+    kinds = [[P, P, P, P], [E, O, P, P], [O, O, O, O], [P, P, WL, WH], [E, O, WL, O], [O, E, E, WH]]
+    cases, budgets = [], []
+    for k in range(24):
+        nx = int(rng.integers(20, 600))
+        ny = int(rng.integers(3, 90))
+        c = W.random_smooth(nx, ny, seed=500 + k, bcs=kinds[rng.integers(len(kinds))], jumps=True,
+                            precision="fp32")
+        cases.append(c)
+        budgets.append(int(rng.integers(0, 45)))
+    cases.append(W.random_smooth(4096, 1024, seed=499, bcs=[E, O, P, P], jumps=True, precision="fp32"))
+    budgets.append(-1)
+    restart = 5
+    with lib.Batch(len(cases), precision="fp32") as b:
+        slots = add_all(b, cases, budgets)
+        for n in (3, 10, 1, 7):
+            b.step(n)
+        b.set_steps(slots[restart], 9)       # 21 steps so far, then 9 more
+        for n in (2, 13, 5, 6):
+            b.step(n)
+        got = [b.get_f(s) for s in slots[:-1]]
+        done = [b.steps_done(s) for s in slots[:-1]]
+    for k, c in enumerate(cases[:-1]):
+        n_expect = min(budgets[k], 21) + 9 if k == restart else min(budgets[k], 47)
+        assert done[k] == (9 if k == restart else n_expect), (k, done[k])
+        with lib.Solver(c["params"]) as single:
+            single.steps_per_launch = 1
+            single.init(c["rho"], c["ux"], c["uy"], c["T"])
+            single.step(n_expect)
+            assert np.array_equal(single.get_f(), got[k]), (k, c["name"], c["params"]["bc"])
