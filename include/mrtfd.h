@@ -232,6 +232,11 @@ int mrtfd_batch_step_timed(mrtfd_batch_t b, long nsteps, double* elapsed_ms);
 long mrtfd_batch_steps_done(mrtfd_batch_t b, int slot);
 int mrtfd_batch_remaining(mrtfd_batch_t b, int slot, long* remaining);
 
+/* Diagnostics: rounds the batch has run since it was created, of one step
+ * and of two steps (see mrtfd_batch_set_steps_per_launch).  MRTFD_EINVAL
+ * for NULL arguments. */
+int mrtfd_batch_rounds(mrtfd_batch_t b, long* one_step, long* two_step);
+
 /* Per-slot outputs and checkpoint, as the single-instance calls. */
 int mrtfd_batch_macros(mrtfd_batch_t b, int slot, double* rho, double* ux, double* uy, double* T,
                        int on_device);

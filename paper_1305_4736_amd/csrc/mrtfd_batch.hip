@@ -100,6 +100,7 @@ struct mrtfd_batch_s {
     bool dirty;
     long L;                             // steps taken by the batch
     long R;                             // rounds (one or two steps each)
+    long rounds1, rounds2;              // one-step and two-step rounds run (diagnostics)
     std::vector<long> rstop;            // R at which a pair slot stopped stepping (LONG_MAX while it steps)
     int per_launch;                     // 2: two-step rounds where possible; 1: one step per round
     double cost[NSHAPE];                // device microseconds per work unit of each class
@@ -372,11 +373,13 @@ int launch_round_t(mrtfd_batch_s* B, bool two)
         if (rc) return rc;
         if (any) HIPCHK(hipStreamWaitEvent(B->stream, B->join, 0));
         B->L += 2;
+        ++B->rounds2;
     } else {
         const int all[] = {0, 1, 2, 3, MARCH};
         int rc = launch_lists<T>(B, all, 5, L0, true, B->stream);
         if (rc) return rc;
         B->L += 1;
+        ++B->rounds1;
     }
     B->R += 1;
     // slots whose budget just ran out leave the work lists (pair slots keep
@@ -744,6 +747,14 @@ long mrtfd_batch_steps_done(mrtfd_batch_t B, int k)
 {
     if (check_slot(B, k)) return -1;
     return std::min(B->L, B->slot[k].stop) - B->slot[k].start;
+}
+
+int mrtfd_batch_rounds(mrtfd_batch_t B, long* one_step, long* two_step)
+{
+    if (!B || !one_step || !two_step) return fail(MRTFD_EINVAL, "NULL argument");
+    *one_step = B->rounds1;
+    *two_step = B->rounds2;
+    return MRTFD_OK;
 }
 
 int mrtfd_batch_remaining(mrtfd_batch_t B, int k, long* remaining)

@@ -288,6 +288,7 @@ _lib.mrtfd_batch_step_timed.argtypes = [_B, ctypes.c_long, _dp]
 _lib.mrtfd_batch_steps_done.argtypes = [_B, ctypes.c_int]
 _lib.mrtfd_batch_steps_done.restype = ctypes.c_long
 _lib.mrtfd_batch_remaining.argtypes = [_B, ctypes.c_int, ctypes.POINTER(ctypes.c_long)]
+_lib.mrtfd_batch_rounds.argtypes = [_B, ctypes.POINTER(ctypes.c_long), ctypes.POINTER(ctypes.c_long)]
 _lib.mrtfd_batch_macros.argtypes = [_B, ctypes.c_int, _vp, _vp, _vp, _vp, ctypes.c_int]
 _lib.mrtfd_batch_get_f.argtypes = [_B, ctypes.c_int, _vp, ctypes.c_int]
 _lib.mrtfd_batch_set_f.argtypes = [_B, ctypes.c_int, _vp, ctypes.c_int]
@@ -383,6 +384,12 @@ class Batch:
         r = ctypes.c_long(0)
         _check(_lib.mrtfd_batch_remaining(self._b, int(slot), ctypes.byref(r)))
         return int(r.value)
+
+    def rounds(self):
+        """(one-step rounds, two-step rounds) run so far (diagnostics)."""
+        one, two = ctypes.c_long(0), ctypes.c_long(0)
+        _check(_lib.mrtfd_batch_rounds(self._b, ctypes.byref(one), ctypes.byref(two)))
+        return int(one.value), int(two.value)
 
     def macros(self, slot: int, out=None):
         shp = self._shapes[slot]

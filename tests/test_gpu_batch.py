@@ -210,6 +210,9 @@ def test_two_step_rounds_match_one_step(lib, precision):
             b.step(20)
             out[k] = ([b.macros(s) if s == slots[10] else b.get_f(s) for s in slots + [s_late]],
                       [b.steps_done(s) for s in slots + [s_late]])
+            one, two = b.rounds()
+            assert (two > 0) if k == 2 else (two == 0), (k, one, two)
+            assert one + 2 * two == 44
     assert out[1][1] == out[2][1]
     assert out[2][1] == [7, 40, 33, 9, 40, 0, 21, 40, 39, 40, 44, 40, 31, 44, 38, 25]
     for a, c, case in zip(out[1][0], out[2][0], cases + [late]):
@@ -316,6 +319,8 @@ def test_random_batch_matches_instances_alone(lib):
             b.step(n)
         got = [b.get_f(s) for s in slots[:-1]]
         done = [b.steps_done(s) for s in slots[:-1]]
+        one, two = b.rounds()
+        assert two > 0 and one + 2 * two == 47, (one, two)
     for k, c in enumerate(cases[:-1]):
         n_expect = min(budgets[k], 21) + 9 if k == restart else min(budgets[k], 47)
         assert done[k] == (9 if k == restart else n_expect), (k, done[k])
