@@ -101,6 +101,8 @@ struct mrtfd_batch_s {
     long L;                             // steps taken by the batch
     long R;                             // rounds (one or two steps each)
     long rounds1, rounds2;              // one-step and two-step rounds run (diagnostics)
+    int mrows;                          // band height of the strip slots' one-step launches
+    bool fit_rows;                      // fit mrows to the load (off for calibration batches)
     std::vector<long> rstop;            // R at which a pair slot stopped stepping (LONG_MAX while it steps)
     int per_launch;                     // 2: two-step rounds where possible; 1: one step per round
     double cost[NSHAPE];                // device microseconds per work unit of each class
@@ -191,7 +193,7 @@ void set_args(mrtfd_batch_s* B, int k)
     const int s = B->shape[k];
     const ShapeDef& sd = SHAPES[s == MARCH ? 0 : s];
     B->slot[k].a = make_args(B->prm[k], B->lay[k], B->blk[k], B->d_blocks + k, B->d_flags + k, sd.txw, sd.byr, 1 << 20);
-    set_march_rows(B->slot[k].a, MBROWS);
+    set_march_rows(B->slot[k].a, B->mrows);
     set_pair_rows(B->slot[k].a, MBROWS2);
     B->slot[k].pair = pair_capable(B, k) ? 1 : 0;
 }
@@ -221,9 +223,53 @@ bool in_list(const mrtfd_batch_s* B, int k, int s)
     return true;
 }
 
+// Band height of the strip slots' one-step launches: the tallest of 12, 6,
+// 3, 2 and 1 rows whose work items fill the resident wavefronts.  A batch
+// too light to fill the device is bound by the rows each wavefront walks
+// (its four window rows plus the band), so it gets shorter bands; heavy
+// batches keep 12.  Bands grow back only once the taller level fills the
+// device 1.5 times over, so a load near a threshold does not flip levels;
+// a change re-uploads the descriptors of the occupied slots in one copy.
+int fit_march_rows(mrtfd_batch_s* B)
+{
+    if (!B->fit_rows) return MRTFD_OK;
+    const long cap = (long)B->march_blocks * MWPB;
+    const int levels[] = {MBROWS, MBROWS / 2, MBROWS / 4, 2, 1};
+    int r = 1;
+    for (int lv : levels) {
+        if (lv < 1) continue;
+        long items = 0;
+        for (int k = 0; k < B->capacity; ++k) {
+            if (!B->used[k] || B->L >= B->slot[k].stop || B->shape[k] != MARCH) continue;
+            const StepArgs& a = B->slot[k].a;
+            items += (long)a.m_nsx * ((a.y1 - a.y0 + lv - 1) / lv);
+        }
+        const long need = (lv > B->mrows) ? cap + cap / 2 : cap;
+        if (items >= need) {
+            r = lv;
+            break;
+        }
+    }
+    if (r == B->mrows) return MRTFD_OK;
+    B->mrows = r;
+    int k0 = B->capacity, k1 = -1;
+    for (int k = 0; k < B->capacity; ++k) {
+        if (!B->used[k]) continue;
+        k0 = std::min(k0, k);
+        k1 = k;
+        if (B->shape[k] == MARCH) set_march_rows(B->slot[k].a, r);
+    }
+    if (k1 >= k0)
+        HIPCHK(hipMemcpyAsync(B->d_slot + k0, &B->slot[k0], (size_t)(k1 - k0 + 1) * sizeof(BatchSlot),
+                              hipMemcpyHostToDevice, B->stream));
+    return MRTFD_OK;
+}
+
 // Rebuild the work lists over slots that still step.
 int rebuild_lists(mrtfd_batch_s* B)
 {
+    int rc = fit_march_rows(B);
+    if (rc) return rc;
     std::vector<int> host(NLIST * (B->capacity + 1) + NLIST * B->capacity + B->capacity, 0);
     B->nwall = 0;
     for (int s = 0; s < NLIST; ++s) {
@@ -526,6 +572,8 @@ int mrtfd_batch_create(int capacity, int precision, int limiter, void* hip_strea
     B->shape.assign(capacity, 0);
     B->rstop.assign(capacity, LONG_MAX);
     B->per_launch = 2;
+    B->mrows = MBROWS;
+    B->fit_rows = true;
     for (int s = 0; s < NSHAPE; ++s) {
         B->cost[s] = DEFAULT_COST[s];
         B->launch_us[s] = 10.0;
@@ -912,6 +960,7 @@ int mrtfd_batch_autotune(mrtfd_batch_t B, double* cost_per_unit_us)
         mrtfd_batch_t C = nullptr;
         int rc = mrtfd_batch_create(1, B->precision, B->limiter, B->stream, &C);
         if (rc) return rc;
+        C->fit_rows = false;     // per-unit costs at the standard band height
         const size_t n = (size_t)p.nx * p.ny;
         std::vector<double> one(n, 1.0), zero(n, 0.0);
         int k = -1;
