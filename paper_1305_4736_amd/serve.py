@@ -97,11 +97,13 @@ class Server:
         budget = free0 - self.reserve
         if self.cap_bytes is not None:
             budget = min(budget, int(self.cap_bytes))
+        budget0 = budget            # the host's bound; `budget` also learns what the device holds
         pending = collections.deque()
         active = {}                 # (precision, slot) -> request record
         resident = 0
         nxt = 0
         lat, done_nodeupd, results, admitted, ticks = [], 0.0, {}, 0, 0
+        rejected = []               # requests the device cannot hold even alone
         max_resident, max_active = 0, 0
         t0 = time.perf_counter()
         while True:
@@ -123,16 +125,37 @@ class Server:
                     t_arr, spec = reqs[i]
                     p = spec["params"]
                     fp = mrtfd.footprint(p)
-                    if mem_blocked or full[p["precision"]] or resident + fp > budget:
-                        mem_blocked = mem_blocked or (resident + fp > budget and not full[p["precision"]])
+                    if fp > budget0:
+                        rejected.append(i)      # larger than the whole budget: would wait forever
+                        continue
+                    # with nothing resident a request is always tried (the
+                    # device decides); otherwise it waits for room
+                    fits = resident == 0 or resident + fp <= budget
+                    if mem_blocked or full[p["precision"]] or not fits:
+                        mem_blocked = mem_blocked or (not fits and not full[p["precision"]])
                         keep.append(i)
                         continue
                     b = self.batches[p["precision"]]
-                    with self._on(p["precision"]):
-                        slot = b.add(p, *self.materialize(spec), nsteps=spec["nsteps"])
+                    try:
+                        with self._on(p["precision"]):
+                            slot = b.add(p, *self.materialize(spec), nsteps=spec["nsteps"])
+                    except mrtfd.MRTFDError as e:
+                        if e.code != mrtfd.ENOMEM:
+                            raise
+                        if resident == 0:
+                            rejected.append(i)  # does not fit even alone
+                            continue
+                        # the device holds less than the footprints add up to
+                        # (allocator rounding and caching): the request waits,
+                        # and what is resident now becomes the budget
+                        budget = min(budget, resident)
+                        mem_blocked = True
+                        keep.append(i)
+                        continue
                     active[(p["precision"], slot)] = {"i": i, "t": t_arr if realtime else 0.0, "fp": fp,
                                                       "nodes": p["nx"] * p["ny"], "steps": spec["nsteps"]}
                     resident += fp
+                    budget = max(budget, resident)
                     admitted += 1
                     full[p["precision"]] = sum(1 for k in active if k[0] == p["precision"]) >= self.capacity
                 pending = keep
@@ -182,7 +205,7 @@ class Server:
         span = max(reqs[-1][0], 1e-9) if (reqs and realtime) else None
         lat_a = np.array(lat) if lat else np.array([np.nan])
         report = {
-            "requests": len(reqs), "admitted": admitted, "completed": len(lat),
+            "requests": len(reqs), "admitted": admitted, "completed": len(lat), "rejected": len(rejected),
             "backlog": len(pending) + (len(reqs) - nxt), "resident_at_end": len(active),
             "p50_s": float(np.percentile(lat_a, 50)), "p99_s": float(np.percentile(lat_a, 99)),
             "mean_s": float(np.mean(lat_a)), "elapsed_s": elapsed, "ticks": ticks,

@@ -2,7 +2,8 @@
 with a stand-in for the library's batches: first come, first served within a
 precision, the memory budget never exceeded and never overtaken, a full batch
 letting the other precision pass, every request stepped exactly its budget,
-and every request answered once."""
+every request answered once, and a device allocation that fails although the
+budget allows it (the request waits; the budget shrinks to what fit)."""
 import pytest
 
 from paper_1305_4736_amd import mrtfd, serve
@@ -139,3 +140,56 @@ def test_request_recipe(seed):
         assert 200 <= s["nsteps"] <= 5000
     ts = [t for t, _ in reqs]
     assert ts == sorted(ts) and 300 <= len(reqs) <= 500     # Poisson, mean 400
+
+
+class TightBatch(FakeBatch):
+    """A device that holds less than the budget: adds fail with ENOMEM once
+    the resident bytes would pass `device_bytes`."""
+
+    def __init__(self, capacity, precision, limiter, ledger, device_bytes):
+        super().__init__(capacity, precision, limiter, ledger)
+        self.device_bytes = device_bytes
+
+    def add(self, p, rho, ux, uy, T, nsteps):
+        if self.ledger["resident"] + mrtfd.footprint(p) > self.device_bytes:
+            self.ledger["refused"] += 1
+            raise mrtfd.MRTFDError(mrtfd.ENOMEM, "cannot allocate")
+        return super().add(p, rho, ux, uy, T, nsteps)
+
+
+def test_allocation_failure_waits_and_shrinks_the_budget():
+    reqs = small_stream(40, seed=5)
+    led = dict(ledger(), refused=0)
+    fps = sorted(mrtfd.footprint(s["params"]) for _, s in reqs)
+    device = sum(fps[-4:])                       # room for about four of them
+    factory = lambda cap, prec, lim: TightBatch(cap, prec, lim, led, device)
+    srv = serve.Server(capacity=64, steps_per_tick=300, reserve_bytes=0, keep_results=True,
+                       batch_factory=factory, memory=(1 << 40, 1 << 40))
+    rep = srv.run(reqs, realtime=False)
+    assert led["refused"] > 0                    # the budget alone would have admitted more
+    assert led["peak"] <= device
+    assert rep["completed"] == len(reqs) == led["finished"]
+    assert sorted(rep["results"]) == list(range(len(reqs)))
+
+
+def test_requests_that_cannot_fit_alone_are_rejected():
+    # one request larger than the device: refused by the device with nothing
+    # resident, it is rejected instead of waiting forever; the rest complete
+    reqs = small_stream(12, seed=6)
+    fps = [mrtfd.footprint(s["params"]) for _, s in reqs]
+    big = max(range(len(reqs)), key=lambda k: fps[k])
+    second = sorted(fps)[-2]
+    device = (second + fps[big]) // 2            # every request fits alone but the largest
+    assert second <= device < fps[big]
+    led = dict(ledger(), refused=0)
+    factory = lambda cap, prec, lim: TightBatch(cap, prec, lim, led, device)
+    srv = serve.Server(capacity=64, steps_per_tick=300, reserve_bytes=0, keep_results=True,
+                       batch_factory=factory, memory=(1 << 40, 1 << 40))
+    rep = srv.run(reqs, realtime=False)
+    assert rep["rejected"] == 1 and big not in rep["results"]
+    assert rep["completed"] == len(reqs) - 1
+    # and by the budget alone, before any allocation
+    led = ledger()
+    srv = make_server(64, device, led)
+    rep = srv.run(reqs, realtime=False)
+    assert rep["rejected"] == 1 and rep["completed"] == len(reqs) - 1
