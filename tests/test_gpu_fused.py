@@ -180,6 +180,30 @@ def test_wall_refill_forms_agree(lib, precision):
             assert np.array_equal(ref, f), (c["name"], form)
 
 
+@pytest.mark.parametrize("axis", ["x", "y"])
+def test_walls_hold_a_matching_uniform_state(lib, axis):
+    # as in the oracle's invariants: a uniform equilibrium moving along NEE
+    # walls at their speed and temperature stays put (walls along y in both
+    # launch forms; along x one step per launch)
+    if axis == "y":
+        w = W.bc("wall", 1.0, 0.1, 0.0, 0.9)
+        bcs, state = [P, P, w, w], (1.3, 0.1, 0.0, 0.9)
+    else:
+        w = W.bc("wall", 1.0, 0.0, -0.08, 0.9)
+        bcs, state = [w, w, P, P], (1.3, 0.0, -0.08, 0.9)
+    c = W.random_smooth(300, 200, seed=4, bcs=bcs)
+    shp = (c["params"]["ny"], c["params"]["nx"])
+    for per_launch in ((1, 2) if axis == "y" else (1,)):
+        with lib.Solver(c["params"]) as s:
+            s.steps_per_launch = per_launch
+            s.init(*[np.full(shp, v) for v in state])
+            f0 = s.get_f()
+            s.step(30)
+            s.sync()
+            f1 = s.get_f()
+        assert np.abs(f1 - f0).max() <= 1e-13 * np.abs(f0).max(), (axis, per_launch)
+
+
 def test_fusion_rules(lib):
     c = W.random_smooth(64, 40, bcs=[WL, WH, P, P])
     with lib.Solver(c["params"]) as s:

@@ -1,6 +1,9 @@
 """Invariants the oracle's full step must satisfy (Sec. II-III).
 
-* a uniform equilibrium state is a fixed point;
+* a uniform equilibrium state is a fixed point, also between NEE walls that
+  move along themselves at the fluid's velocity and temperature (the wall
+  node then equals its neighbour: any mistake in the wall's velocity,
+  temperature or pressure carry-over moves it);
 * on a periodic grid mass, momentum and energy (rows 1..4 of M) are conserved
   to round-off (the collision leaves them untouched, the fluxes telescope);
 * a 90 degree rotation and a mirror of the initial state rotate / mirror the
@@ -21,6 +24,30 @@ def test_uniform_state_is_fixed_point(orc):
     f0 = orc.init(p, 1.3, 0.11, -0.07, 0.9)
     f1 = orc.advance(p, f0, 20)
     assert np.abs(f1 - f0).max() <= 1e-14 * np.abs(f0).max() * 20
+
+
+@pytest.mark.parametrize("axis", ["x", "y"])
+def test_walls_hold_a_matching_uniform_state(orc, axis):
+    # walls along `axis`... the fluid moves along them at their speed, at a
+    # density other than the walls' nominal one (the wall density follows the
+    # pressure of the fluid node next to it)
+    P = W.bc("periodic")
+    if axis == "y":
+        w = W.bc("wall", 1.0, 0.1, 0.0, 0.9)
+        bcs, state = [P, P, w, w], (1.3, 0.1, 0.0, 0.9)
+    else:
+        w = W.bc("wall", 1.0, 0.0, -0.08, 0.9)
+        bcs, state = [w, w, P, P], (1.3, 0.0, -0.08, 0.9)
+    c = W.random_smooth(12, 10, seed=4, bcs=bcs)
+    p = c["params"]
+    f0 = orc.init(p, *state)
+    f1 = orc.advance(p, f0, 30)
+    assert np.abs(f1 - f0).max() <= 1e-13 * np.abs(f0).max()
+    # and a wall whose temperature differs from the fluid's does move it
+    w2 = W.bc("wall", 1.0, w["state"][1], w["state"][2], 1.0)
+    p2 = dict(p, bc=[w2 if b["kind"] == "wall" else b for b in p["bc"]])
+    f2 = orc.advance(p2, orc.init(p2, *state), 30)
+    assert np.abs(f2 - f0).max() > 1e-6 * np.abs(f0).max()
 
 
 def _totals(orc, p, f):
