@@ -2,8 +2,8 @@
 
 * a uniform equilibrium state is a fixed point, also between NEE walls that
   move along themselves at the fluid's velocity and temperature (the wall
-  node then equals its neighbour: any mistake in the wall's velocity,
-  temperature or pressure carry-over moves it);
+  node then equals its neighbour; a wall that takes a wrong velocity
+  component or sign, a wrong temperature or its nominal density moves it);
 * on a periodic grid mass, momentum and energy (rows 1..4 of M) are conserved
   to round-off (the collision leaves them untouched, the fluxes telescope);
 * a 90 degree rotation and a mirror of the initial state rotate / mirror the

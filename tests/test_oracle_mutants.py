@@ -34,6 +34,12 @@ MUTANTS = [
     ("matrix_row_14_term", "out[13] = c2 * ce;", "out[13] = ce * ce;"),
     ("eta_on_wrong_group", "C->eta[i] = (g == 0) ? eta0 : 0.0;", "C->eta[i] = (g == 1) ? eta0 : 0.0;"),
     ("wall_density", "double rw = r1 * T1 / st[3];", "double rw = r1;"),
+    ("wall_velocity_ignored", "feq_velocity(C, p->b, rw, st[1], st[2], st[3], eqw);",
+     "feq_velocity(C, p->b, rw, u1x, u1y, st[3], eqw);"),
+    ("wall_nonequilibrium_dropped", "for (int i = 0; i < Q; ++i) fw[i] = eqw[i] + (f1[i] - eq1[i]);",
+     "for (int i = 0; i < Q; ++i) fw[i] = eqw[i] + 0.0 * (f1[i] - eq1[i]);"),
+    ("wall_ghosts_constant", "for (int i = 0; i < Q; ++i) gk[i] = (k + 1) * fw[i] - k * f1[i];",
+     "for (int i = 0; i < Q; ++i) gk[i] = fw[i] + 0.0 * k * f1[i];"),
 ]
 
 # the pins, cheapest first
@@ -45,6 +51,8 @@ PINS = [
     lambda o: T_const.test_feq_hat_consistent_with_velocity_space(o),
     lambda o: T_const.test_eta_enters_only_through_m(o),
     lambda o: T_inv.test_uniform_state_is_fixed_point(o),
+    lambda o: T_inv.test_walls_hold_a_matching_uniform_state(o, "y"),
+    lambda o: T_inv.test_walls_hold_a_matching_uniform_state(o, "x"),
     lambda o: T_inv.test_conservation_periodic(o, "mc"),
     lambda o: T_inv.test_rotation_symmetry(o),
     lambda o: T_inv.test_mirror_symmetry(o),
