@@ -10,7 +10,11 @@
   solution (catches any x/y or index mix-up in the split fluxes);
 * an nx x 1 run equals every row of an nx x 8 run with y-uniform data;
 * outflow and equilibrium boundaries do not disturb nodes the waves have not
-  reached (domain of dependence of the explicit stencil).
+  reached (domain of dependence of the explicit stencil);
+* one step with an outflow or equilibrium side equals one step on a grid
+  extended by four lines that hold what the ghosts stand for (copies of the
+  last line; the side's equilibrium), on the original nodes: the stencil
+  reaches two lines out, so this pins which values the ghosts take.
 """
 import numpy as np
 import pytest
@@ -135,3 +139,32 @@ def test_boundaries_do_not_act_ahead_of_waves(orc):
         assert np.abs(o[:, :, inner] - outs[0][:, :, inner]).max() == 0.0
     # and the periodic wrap does differ near the edges
     assert np.abs(outs[2] - outs[0]).max() > 1e-8
+
+
+@pytest.mark.parametrize("kind", ["outflow", "equilibrium"])
+@pytest.mark.parametrize("axis", ["x", "y"])
+def test_ghosts_act_as_the_lines_they_stand_for(orc, kind, axis):
+    E = W.bc("equilibrium", 1.1, 0.05, -0.02, 0.9)
+    P, O = W.bc("periodic"), W.bc("outflow")
+    bcs = [P, P, P, P]
+    lo, hi = (0, 1) if axis == "x" else (2, 3)
+    bcs[lo], bcs[hi] = O, (O if kind == "outflow" else E)
+    nx, ny = 20, 14
+    c = W.random_smooth(nx, ny, seed=8, bcs=bcs, jumps=True)
+    p = c["params"]
+    f = orc.init(p, c["rho"], c["ux"], c["uy"], c["T"])
+    g = orc.advance(p, f, 1)
+    # the same state on a grid four lines longer past the side under test
+    ax = 2 if axis == "x" else 1                 # f is (plane, y, x)
+    if kind == "outflow":
+        last = np.take(f, [-1], axis=ax)
+        extra = np.repeat(last, 4, axis=ax)
+    else:
+        line = dict(p, nx=4 if axis == "x" else nx, ny=ny if axis == "x" else 4,
+                    bc=[P, P, P, P])
+        extra = orc.init(line, *E["state"])
+    fe = np.concatenate([f, extra], axis=ax)
+    pe = dict(p, nx=nx + 4 if axis == "x" else nx, ny=ny + 4 if axis == "y" else ny)
+    ge = orc.advance(pe, fe, 1)
+    ge = ge[:, :, :nx] if axis == "x" else ge[:, :ny, :]
+    assert np.abs(ge - g).max() <= 1e-13 * np.abs(g).max()

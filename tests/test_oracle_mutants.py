@@ -17,6 +17,12 @@ import test_oracle_textbook as T_text
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "mrtfd_oracle.c")
 
+# the equilibrium ghost state of the x sides (the y sides' line reads the same)
+EQX = """/* x-lo, x-hi */
+        int kind = p->bc_kind[side];
+        const double* st = p->bc_state[side];
+        if (kind == ORC_BC_EQUILIBRIUM) feq_velocity(C, p->b, st[0], st[1], st[2], st[3], eq);"""
+
 # (name, original text, planted mistake)
 MUTANTS = [
     ("correction_8_sign", "R[7] += C8;", "R[7] -= C8;"),
@@ -40,6 +46,11 @@ MUTANTS = [
      "for (int i = 0; i < Q; ++i) fw[i] = eqw[i] + 0.0 * (f1[i] - eq1[i]);"),
     ("wall_ghosts_constant", "for (int i = 0; i < Q; ++i) gk[i] = (k + 1) * fw[i] - k * f1[i];",
      "for (int i = 0; i < Q; ++i) gk[i] = fw[i] + 0.0 * k * f1[i];"),
+    ("outflow_x_copies_second_node", "load_node(g, side == 0 ? 0 : nx - 1, y, tmp);",
+     "load_node(g, side == 0 ? 1 : nx - 2, y, tmp);"),
+    ("outflow_y_copies_second_node", "load_node(g, x, side == 2 ? 0 : ny - 1, tmp);",
+     "load_node(g, x, side == 2 ? 1 : ny - 2, tmp);"),
+    ("equilibrium_x_velocity_swapped", EQX, EQX.replace("st[1], st[2], st[3], eq", "st[2], st[1], st[3], eq")),
 ]
 
 # the pins, cheapest first
@@ -57,6 +68,10 @@ PINS = [
     lambda o: T_inv.test_rotation_symmetry(o),
     lambda o: T_inv.test_mirror_symmetry(o),
     lambda o: T_inv.test_boundaries_do_not_act_ahead_of_waves(o),
+    lambda o: T_inv.test_ghosts_act_as_the_lines_they_stand_for(o, "outflow", "x"),
+    lambda o: T_inv.test_ghosts_act_as_the_lines_they_stand_for(o, "outflow", "y"),
+    lambda o: T_inv.test_ghosts_act_as_the_lines_they_stand_for(o, "equilibrium", "x"),
+    lambda o: T_inv.test_ghosts_act_as_the_lines_they_stand_for(o, "equilibrium", "y"),
     lambda o: T_noneq.test_zero_at_equilibrium(o),
     lambda o: T_noneq.test_star_equals_plain_at_rest(o),
     lambda o: T_text.test_unit_courant_is_exact_shift(o),
