@@ -51,6 +51,10 @@ MUTANTS = [
     ("outflow_y_copies_second_node", "load_node(g, x, side == 2 ? 0 : ny - 1, tmp);",
      "load_node(g, x, side == 2 ? 1 : ny - 2, tmp);"),
     ("equilibrium_x_velocity_swapped", EQX, EQX.replace("st[1], st[2], st[3], eq", "st[2], st[1], st[3], eq")),
+    ("gradient_x_uses_dy", "double duxdx = (ux[UIX(x + 1, y)] - ux[UIX(x - 1, y)]) / (2.0 * p->dx);",
+     "double duxdx = (ux[UIX(x + 1, y)] - ux[UIX(x - 1, y)]) / (2.0 * p->dy);"),
+    ("courant_spacings_swapped", "double nu = p->dt / (C->A[i] * ((a == 0) ? p->dx : p->dy));",
+     "double nu = p->dt / (C->A[i] * ((a == 0) ? p->dy : p->dx));"),
 ]
 
 # the pins, cheapest first
@@ -66,6 +70,7 @@ PINS = [
     lambda o: T_inv.test_walls_hold_a_matching_uniform_state(o, "x"),
     lambda o: T_inv.test_conservation_periodic(o, "mc"),
     lambda o: T_inv.test_rotation_symmetry(o),
+    lambda o: T_inv.test_rotation_symmetry_with_unequal_spacings(o),
     lambda o: T_inv.test_mirror_symmetry(o),
     lambda o: T_inv.test_boundaries_do_not_act_ahead_of_waves(o),
     lambda o: T_inv.test_ghosts_act_as_the_lines_they_stand_for(o, "outflow", "x"),
@@ -75,6 +80,7 @@ PINS = [
     lambda o: T_noneq.test_zero_at_equilibrium(o),
     lambda o: T_noneq.test_star_equals_plain_at_rest(o),
     lambda o: T_text.test_unit_courant_is_exact_shift(o),
+    lambda o: T_text.test_unit_courant_is_exact_shift_with_unequal_spacings(o),
     lambda o: T_text.test_reduces_to_textbook_limited_scheme(o, "lw"),
     lambda o: T_text.test_reduces_to_textbook_limited_scheme(o, "minmod"),
     lambda o: T_text.test_reduces_to_textbook_limited_scheme(o, "mc"),

@@ -22,10 +22,10 @@ from paper_1305_4736_amd import workloads as W
 NX = 24
 
 
-def _free_streaming_case(limiter, dt):
+def _free_streaming_case(limiter, dt, dy_over_dx=1.0):
     d = 1.0 / NX
     s = [0.0] * 16
-    p = W.make_params(NX, 1, d, d, dt, s, 5.0, [W.bc("periodic")] * 4, limiter=limiter,
+    p = W.make_params(NX, 1, d, dy_over_dx * d, dt, s, 5.0, [W.bc("periodic")] * 4, limiter=limiter,
                       correction=False)
     return p
 
@@ -91,10 +91,10 @@ def test_reduces_to_textbook_limited_scheme(orc, limiter):
         assert np.abs(f1[i, 0] - ref).max() < 1e-14 * (1 + np.abs(q).max()), (limiter, i)
 
 
-def test_unit_courant_is_exact_shift(orc):
+def test_unit_courant_is_exact_shift(orc, dy_over_dx=1.0):
     dt = (1.0 / NX) / 6.0
     for limiter in ("mc", "minmod", "lw", "upwind"):
-        p = _free_streaming_case(limiter, dt)
+        p = _free_streaming_case(limiter, dt, dy_over_dx)
         f0 = _random_f(orc, p, 2)
         f1 = orc.advance(p, f0, 1)
         vx = _vx(orc)
@@ -103,6 +103,11 @@ def test_unit_courant_is_exact_shift(orc):
                 shift = 1 if vx[i] > 0 else -1
                 ref = np.roll(f0[i], shift, axis=1)
                 assert np.abs(f1[i] - ref).max() <= 4e-16 * np.abs(f0[i]).max() * 4
+
+
+def test_unit_courant_is_exact_shift_with_unequal_spacings(orc):
+    # the shift along x depends on dx alone (the one-row y axis is inert)
+    test_unit_courant_is_exact_shift(orc, dy_over_dx=2.0)
 
 
 @pytest.mark.parametrize("limiter", ["minmod", "mc"])
