@@ -94,6 +94,36 @@ def test_other_limiters_fp64(lib, orc, limiter):
     check_case(lib, orc, case)
 
 
+def anisotropic(case, ratio=1.6):
+    # dy = ratio dx, dt within the unsplit Courant bound of the smaller spacing
+    p = dict(case["params"])
+    p.update(dy=ratio * p["dx"], dt=0.3 * p["dx"] / 6.0)
+    return dict(case, params=p, name=case["name"] + "_dy%.1fdx" % ratio)
+
+
+@pytest.mark.parametrize("bcs", ["inflow_outflow", "walls_y", "walls_x", "outflow_x_eq_y"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_unequal_spacings(lib, orc, bcs, precision):
+    # every other test has dy = dx: a spacing taken for the other axis (in the
+    # Courant numbers or the velocity gradients of the correction) would pass
+    # them; here dy = 1.6 dx, one and two steps per launch and in a batch
+    case = anisotropic(W.random_smooth(130, 61, seed=31, bcs=BC_SETS[bcs], jumps=True, nsteps=20))
+    check_case(lib, orc, case, precision)
+    mo, _ = run_orc(orc, case)
+    p = dict(case["params"], precision=precision)
+    if bcs != "walls_x":
+        with lib.Solver(p) as s:
+            s.steps_per_launch = 2
+            s.init(case["rho"], case["ux"], case["uy"], case["T"])
+            s.step(20)
+            s.sync()
+            assert_parity(s.macros(), mo, TOL[precision], gamma_of(case), case["name"] + " fused")
+    with lib.Batch(1, precision=precision) as b:
+        k = b.add(p, case["rho"], case["ux"], case["uy"], case["T"], nsteps=20)
+        b.step(20)
+        assert_parity(b.macros(k), mo, TOL[precision], gamma_of(case), case["name"] + " batch")
+
+
 def test_correction_off_fp64(lib, orc):
     case = W.random_smooth(40, 40, seed=12, bcs=BC_SETS["walls_y"], correction=False, nsteps=20)
     check_case(lib, orc, case)
