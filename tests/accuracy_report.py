@@ -1,6 +1,6 @@
 """Accuracy of every workload against the FP64 oracle, as a table.
 
-    python tests/accuracy_report.py        (needs the GPU and the built library)
+    python tests/accuracy_report.py [--json PATH]   (needs the GPU and the built library)
 
 Runs each configuration on the GPU through the C ABI and the same inputs
 through the serial FP64 oracle, and prints the relative L1 and Linf errors
@@ -249,9 +249,8 @@ def main():
     print("\nFP32 storage against FP64 storage (both on the GPU):\n")
     for r in FP32_ROWS:
         print(json.dumps(r))
-    out = os.path.join(os.path.dirname(HERE), "gpurun_out")
-    if os.path.isdir(out):
-        with open(os.path.join(out, "accuracy.json"), "w") as fh:
+    if "--json" in sys.argv:
+        with open(sys.argv[sys.argv.index("--json") + 1], "w") as fh:
             json.dump({"against_oracle": ROWS, "fp32_against_fp64": FP32_ROWS}, fh, indent=1)
 
 
