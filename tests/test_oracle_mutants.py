@@ -23,6 +23,9 @@ EQX = """/* x-lo, x-hi */
         const double* st = p->bc_state[side];
         if (kind == ORC_BC_EQUILIBRIUM) feq_velocity(C, p->b, st[0], st[1], st[2], st[3], eq);"""
 
+# the row of M* at the relative velocity of population i
+STAR = "if (star) moment_row_values(C.vx[i] - vx, C.vy[i] - vy, C.eta[i], row);"
+
 # (name, original text, planted mistake)
 MUTANTS = [
     ("correction_8_sign", "R[7] += C8;", "R[7] -= C8;"),
@@ -55,6 +58,11 @@ MUTANTS = [
      "double duxdx = (ux[UIX(x + 1, y)] - ux[UIX(x - 1, y)]) / (2.0 * p->dy);"),
     ("courant_spacings_swapped", "double nu = p->dt / (C->A[i] * ((a == 0) ? p->dx : p->dy));",
      "double nu = p->dt / (C->A[i] * ((a == 0) ? p->dy : p->dx));"),
+    ("noneq_star_relative_velocity_sign", STAR, STAR.replace("C.vx[i] - vx", "C.vx[i] + vx")),
+    ("noneq_star_components_swapped", STAR, STAR.replace("C.vx[i] - vx, C.vy[i] - vy", "C.vy[i] - vy, C.vx[i] - vx")),
+    ("noneq_star_eta_dropped", STAR, STAR.replace("C.eta[i], row", "0.0, row")),
+    ("noneq_without_equilibrium", "for (int i = 0; i < Q; ++i) gneq[i] = fl[i] - fe[i];",
+     "for (int i = 0; i < Q; ++i) gneq[i] = fl[i] - 0.0 * fe[i];"),
 ]
 
 # the pins, cheapest first
@@ -79,6 +87,8 @@ PINS = [
     lambda o: T_inv.test_ghosts_act_as_the_lines_they_stand_for(o, "equilibrium", "y"),
     lambda o: T_noneq.test_zero_at_equilibrium(o),
     lambda o: T_noneq.test_star_equals_plain_at_rest(o),
+    lambda o: T_noneq.test_conserved_components_vanish(o),
+    lambda o: T_noneq.test_central_moment_shift_identities(o),
     lambda o: T_text.test_unit_courant_is_exact_shift(o),
     lambda o: T_text.test_unit_courant_is_exact_shift_with_unequal_spacings(o),
     lambda o: T_text.test_reduces_to_textbook_limited_scheme(o, "lw"),
