@@ -1,7 +1,8 @@
 """Host-side checks of the C-ABI library (no GPU needed): it loads, exports
 every entry point include/mrtfd.h declares, its factored constants give the
-paper's M (Appendix) and a true inverse, and parameter validation rejects
-what it should."""
+paper's M (Appendix) and a true inverse, parameter validation rejects
+what it should, the binding refuses to import without the library, and no
+module of the package reaches the oracle."""
 import os
 import re
 
@@ -64,3 +65,31 @@ def test_footprint_and_validation(lib):
             lib.footprint(q)
         assert e.value.code == lib.EINVAL
         assert lib._lib.mrtfd_last_error().decode()
+
+
+def test_binding_without_the_library_fails_loudly(tmp_path):
+    # the product path has no CPU fallback: with the library absent the
+    # binding and everything above it refuse to import
+    import subprocess
+    import sys
+    env = dict(os.environ, MRTFD_LIBRARY=str(tmp_path / "absent" / "libmrtfd.so"))
+    for mod in ("paper_1305_4736_amd.mrtfd", "paper_1305_4736_amd.serve"):
+        r = subprocess.run([sys.executable, "-c", f"import {mod}"], cwd=ROOT, env=env,
+                           capture_output=True, text=True, timeout=300)
+        assert r.returncode != 0, mod
+        assert "ImportError" in r.stderr and "no CPU fallback" in r.stderr, r.stderr[-500:]
+
+
+def test_package_never_reaches_the_oracle():
+    # the oracle is test infrastructure: no module of the package imports,
+    # loads or runs anything under oracle/
+    pkg = os.path.join(ROOT, "paper_1305_4736_amd")
+    hits = []
+    for dirpath, _, files in os.walk(pkg):
+        for name in files:
+            if name.endswith((".py", ".hip", ".h", ".cpp")):
+                path = os.path.join(dirpath, name)
+                for n, line in enumerate(open(path, encoding="utf-8"), 1):
+                    if re.search(r"\boracle\b", line) and re.search(r"import|CDLL|open\(|subprocess|#include|liboracle", line):
+                        hits.append(f"{path}:{n}: {line.strip()}")
+    assert not hits, hits
