@@ -329,3 +329,37 @@ def test_random_batch_matches_instances_alone(lib):
             single.init(c["rho"], c["ux"], c["uy"], c["T"])
             single.step(n_expect)
             assert np.array_equal(single.get_f(), got[k]), (k, c["name"], c["params"]["bc"])
+
+
+def test_full_riemann_batch_as_benchmarked(lib, orc):
+    # the whole seeded 512-instance batch (28.5 M nodes) built and autotuned
+    # as the benchmark builds it, 13 steps (two-step rounds and a last
+    # one-step launch); twelve instances spread over all sizes, the largest
+    # included, end bitwise equal to their instance run alone one step per
+    # launch, and the three smallest of them match the oracle
+    cases, _ = W.riemann_batch(n=512, precision="fp32")
+    n = 13
+    with lib.Batch(len(cases), precision="fp32", limiter="mc") as b:
+        slots = add_all(b, cases)
+        b.autotune()
+        b.step(n)
+        b.status()
+        one, two = b.rounds()
+        order = sorted(range(len(cases)), key=lambda k: cases[k]["params"]["nx"] * cases[k]["params"]["ny"])
+        pick = [order[round(i * (len(order) - 1) / 11)] for i in range(12)]
+        got = {k: b.get_f(slots[k]) for k in pick}
+        mac = {k: b.macros(slots[k]) for k in pick[:3]}
+    assert two > 0 and one + 2 * two == n, (one, two)
+    for k in pick:
+        c = cases[k]
+        with lib.Solver(c["params"]) as single:
+            single.steps_per_launch = 1
+            single.init(c["rho"], c["ux"], c["uy"], c["T"])
+            single.step(n)
+            assert np.array_equal(single.get_f(), got[k]), (k, c["params"]["nx"], c["params"]["ny"])
+    for k in pick[:3]:
+        c = cases[k]
+        p64 = dict(c["params"], precision="fp64")
+        mo = orc.macros(p64, orc.run(p64, c["rho"], c["ux"], c["uy"], c["T"], n))
+        gamma = (c["params"]["b"] + 2.0) / c["params"]["b"]
+        assert_parity(mac[k], mo, TOL["fp32"], gamma, f"{c['name']} {c['params']['nx']}x{c['params']['ny']}")
