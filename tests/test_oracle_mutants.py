@@ -26,6 +26,10 @@ EQX = """/* x-lo, x-hi */
 # the row of M* at the relative velocity of population i
 STAR = "if (star) moment_row_values(C.vx[i] - vx, C.vy[i] - vy, C.eta[i], row);"
 
+# the outgoing and incoming limited face values along one axis
+FACES = """                    double Fout = fJ + 0.5 * (1.0 - nu) * limited_jump(p->limiter, fJm1, fJ, fJp1);
+                    double Fin = fJm1 + 0.5 * (1.0 - nu) * limited_jump(p->limiter, fJm2, fJm1, fJ);"""
+
 # (name, original text, planted mistake)
 MUTANTS = [
     ("correction_8_sign", "R[7] += C8;", "R[7] -= C8;"),
@@ -63,6 +67,12 @@ MUTANTS = [
     ("noneq_star_eta_dropped", STAR, STAR.replace("C.eta[i], row", "0.0, row")),
     ("noneq_without_equilibrium", "for (int i = 0; i < Q; ++i) gneq[i] = fl[i] - fe[i];",
      "for (int i = 0; i < Q; ++i) gneq[i] = fl[i] - 0.0 * fe[i];"),
+    ("mc_cap", "        return 2.0;\n    case ORC_LIM_MINMOD:", "        return 1.0;\n    case ORC_LIM_MINMOD:"),
+    ("mc_middle_half_dropped", "if (theta <= 3.0) return (1.0 + theta) / 2.0;",
+     "if (theta <= 3.0) return (1.0 + theta);"),
+    ("theta_inverted", "double theta = (f0 - fm) / den;",
+     "double theta = (f0 - fm) == 0.0 ? 1e300 : den / (f0 - fm);"),
+    ("courant_factor_sign", FACES, FACES.replace("(1.0 - nu)", "(1.0 + nu)")),
 ]
 
 # the pins, cheapest first
