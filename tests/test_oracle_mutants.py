@@ -73,6 +73,12 @@ MUTANTS = [
     ("theta_inverted", "double theta = (f0 - fm) / den;",
      "double theta = (f0 - fm) == 0.0 ? 1e300 : den / (f0 - fm);"),
     ("courant_factor_sign", FACES, FACES.replace("(1.0 - nu)", "(1.0 + nu)")),
+    ("relaxation_skips_first_nonconserved", "for (int k = 4; k < Q; ++k) R[k] = p->s[k] * (fh[k] - fe[k]);",
+     "for (int k = 5; k < Q; ++k) R[k] = p->s[k] * (fh[k] - fe[k]);"),
+    ("correction_ratio_inverted", "double k8 = p->s[7] / p->s[4] - 1.0;", "double k8 = p->s[4] / p->s[7] - 1.0;"),
+    ("collision_transposed", "for (int k = 0; k < Q; ++k) coll += C->Minv[i][k] * R[k];",
+     "for (int k = 0; k < Q; ++k) coll += C->Minv[k][i] * R[k];"),
+    ("collision_sign", "fnew[i] = f[i] - conv - p->dt * coll;", "fnew[i] = f[i] - conv + p->dt * coll;"),
 ]
 
 # the pins, cheapest first
