@@ -79,6 +79,11 @@ MUTANTS = [
     ("collision_transposed", "for (int k = 0; k < Q; ++k) coll += C->Minv[i][k] * R[k];",
      "for (int k = 0; k < Q; ++k) coll += C->Minv[k][i] * R[k];"),
     ("collision_sign", "fnew[i] = f[i] - conv - p->dt * coll;", "fnew[i] = f[i] - conv + p->dt * coll;"),
+    ("feq_13_pressure_sign", "out[12] = (-2.0 * P + jx", "out[12] = (2.0 * P + jx"),
+    ("feq_14_b_coefficient", "(6.0 + b) * T * j2", "(4.0 + b) * T * j2"),
+    ("feq_16_b_coefficient", "out[15] = ((b + 4.0) * P", "out[15] = ((b + 2.0) * P"),
+    ("energy_with_b_fixed_at_2", "double e = rho * (b * T + ux * ux + uy * uy);",
+     "double e = rho * (2.0 * T + ux * ux + uy * uy);"),
 ]
 
 # the pins, cheapest first
