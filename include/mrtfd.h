@@ -65,7 +65,12 @@ enum { MRTFD_LIM_MC = 0, MRTFD_LIM_MINMOD = 1, MRTFD_LIM_LW = 2, MRTFD_LIM_UPWIN
 
 /* Storage precision: FP64 everywhere, or f stored and convected in FP32 with
  * the conserved-moment sums, temperature, equilibria, collision and the
- * M / M^-1 constants in FP64. */
+ * M / M^-1 constants in FP64.  FP32 storage also stores, per node, the FP64
+ * conserved moments (rho, j_x, j_y, e) of the populations each step
+ * computes before rounding them, and every step first puts the rounded
+ * populations back onto those moments: rounding to FP32 then never moves
+ * mass, momentum or energy (96 bytes per node and buffer, against 128 in
+ * FP64 storage). */
 enum { MRTFD_FP64 = 0, MRTFD_FP32_STORAGE = 1 };
 
 typedef struct {
@@ -147,11 +152,25 @@ int mrtfd_macros(mrtfd_t h, double* rho, double* ux, double* uy, double* T, int 
  * v - u (Appendix).  Output: (16, ny, nx). */
 int mrtfd_noneq(mrtfd_t h, int star, double* delta, int on_device);
 
-/* Checkpoint: copy the interior distribution out / in, (16, ny, nx) doubles
- * (FP32 storage converts exactly on the way out, rounds on the way in).
- * mrtfd_set_f refills ghosts and wall nodes. */
+/* The interior distribution as FP64 populations, out / in, (16, ny, nx)
+ * doubles.  FP32 storage keeps each node as its populations rounded to FP32
+ * plus the FP64 conserved moments (rho, j_x, j_y, e) of the populations
+ * they were rounded from; mrtfd_get_f gives the rounded populations with
+ * their conserved moments put back onto the stored ones, mrtfd_set_f rounds
+ * the populations and stores their conserved moments.  mrtfd_set_f refills
+ * ghosts and wall nodes. */
 int mrtfd_get_f(mrtfd_t h, double* f, int on_device);
 int mrtfd_set_f(mrtfd_t h, const double* f, int on_device);
+
+/* Checkpoint of the stored state, bit for bit: (nplanes, ny, nx) doubles,
+ * the 16 stored populations (exact in FP64) followed, in FP32 storage, by
+ * the 4 stored conserved moments.  mrtfd_state_planes gives nplanes (16 in
+ * FP64 storage, 20 in FP32 storage).  mrtfd_set_state refills ghosts and
+ * wall nodes; stepping on from it gives the same bits as stepping on from
+ * the state it was taken from. */
+int mrtfd_state_planes(mrtfd_t h, int* nplanes);
+int mrtfd_get_state(mrtfd_t h, double* state, int on_device);
+int mrtfd_set_state(mrtfd_t h, const double* state, int on_device);
 
 /* Wait for the handle's stream; returns MRTFD_ENONFINITE (and clears the
  * flag) if any updated node saw rho <= 0, T <= 0 or NaN since the last
@@ -170,6 +189,16 @@ const char* mrtfd_last_error(void);
 /* Free and total device memory of the current device in bytes (for
  * admission by free HBM). */
 int mrtfd_device_memory(size_t* free_bytes, size_t* total_bytes);
+
+/* Diagnostics: enqueue on hip_stream (a hipStream_t) a kernel of one block
+ * per XCD that writes, to the device array out[16], each XCD's shader-clock
+ * counter (core clock cycles; out[2 x]) and the constant-rate 100 MHz
+ * counter (out[2 x + 1]), x the XCD number.  Two stamps around a stretch of
+ * launches give the core clock each XCD ran at: cycles / (ticks / 1e8)
+ * (the clock counters of different XCDs are not aligned; pairs a stamp did
+ * not write keep their old contents).  Asynchronous; read out after the
+ * stream has finished. */
+int mrtfd_clock_stamp(void* hip_stream, unsigned long long* out);
 
 /* Host-only: the dense 16x16 M and M^-1 (row-major) the kernels use in their
  * factored form (per-group angular sums times small blocks), for checks. */

@@ -238,10 +238,34 @@ int refill(mrtfd_s* h)
     return (h->p.precision == MRTFD_FP32_STORAGE) ? refill_t<float>(h) : refill_t<double>(h);
 }
 
+// Diagnostics: the core clock a stretch of launches ran at.  Each block's
+// first lane records its XCD's shader-clock counter and the device-wide
+// constant 100 MHz counter in that XCD's pair of out[16] (the shader-clock
+// counters of different XCDs are not aligned, so a clock is only measured
+// between two stamps of the same XCD).  Launched with one block per XCD.
+__global__ void k_clock_stamp(unsigned long long* out)
+{
+    if (threadIdx.x == 0) {
+        const unsigned xcc = __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 7;   // HW_REG_XCC_ID
+        const unsigned long long t = __builtin_amdgcn_s_memtime();
+        const unsigned long long r = __builtin_amdgcn_s_memrealtime();
+        out[2 * xcc] = t;
+        out[2 * xcc + 1] = r;
+    }
+}
+
 }  // namespace
 
 // ===========================================================================
 extern "C" {
+
+int mrtfd_clock_stamp(void* hip_stream, unsigned long long* out)
+{
+    if (!out) return fail(MRTFD_EINVAL, "NULL argument");
+    hipLaunchKernelGGL(k_clock_stamp, dim3(8), dim3(64), 0, (hipStream_t)hip_stream, out);
+    HIPCHK(hipGetLastError());
+    return MRTFD_OK;
+}
 
 const char* mrtfd_last_error(void) { return error_buffer().c_str(); }
 
@@ -501,6 +525,66 @@ int mrtfd_set_f(mrtfd_t h, const double* f, int on_device)
         hipLaunchKernelGGL((k_scatter<float>), grid, block, 0, h->stream, (float*)h->buf[0], src, h->args);
     else
         hipLaunchKernelGGL((k_scatter<double>), grid, block, 0, h->stream, (double*)h->buf[0], src, h->args);
+    HIPCHK(hipGetLastError());
+    int rc = refill(h);
+    if (rc) return rc;
+    HIPCHK(hipMemsetAsync(h->flag, 0, sizeof(int), h->stream));
+    if (!on_device) HIPCHK(hipStreamSynchronize(h->stream));
+    h->ready = true;
+    h->steps = 0;
+    return MRTFD_OK;
+}
+
+int mrtfd_state_planes(mrtfd_t h, int* nplanes)
+{
+    if (!h || !nplanes) return fail(MRTFD_EINVAL, "NULL argument");
+    *nplanes = (h->p.precision == MRTFD_FP32_STORAGE) ? NQ + 4 : NQ;
+    return MRTFD_OK;
+}
+
+int mrtfd_get_state(mrtfd_t h, double* state, int on_device)
+{
+    if (!h || !state) return fail(MRTFD_EINVAL, "NULL argument");
+    if (!h->ready) return fail(MRTFD_ESTATE, "mrtfd_get_state before mrtfd_init / mrtfd_set_f");
+    const int np = (h->p.precision == MRTFD_FP32_STORAGE) ? NQ + 4 : NQ;
+    const size_t n = (size_t)h->p.nx * h->p.ny;
+    double* dst = state;
+    if (!on_device) {
+        int rc = ensure_staging(h, np * n * sizeof(double));
+        if (rc) return rc;
+        dst = h->staging;
+    }
+    dim3 grid = node_grid(h->p.nx, h->p.ny), block(BX, BY);
+    if (h->p.precision == MRTFD_FP32_STORAGE)
+        hipLaunchKernelGGL((k_gather_state<float>), grid, block, 0, h->stream, (const float*)h->buf[h->cur], dst, h->args);
+    else
+        hipLaunchKernelGGL((k_gather_state<double>), grid, block, 0, h->stream, (const double*)h->buf[h->cur], dst, h->args);
+    HIPCHK(hipGetLastError());
+    if (!on_device) {
+        HIPCHK(hipMemcpyAsync(state, h->staging, np * n * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+    }
+    return MRTFD_OK;
+}
+
+int mrtfd_set_state(mrtfd_t h, const double* state, int on_device)
+{
+    if (!h || !state) return fail(MRTFD_EINVAL, "NULL argument");
+    const int np = (h->p.precision == MRTFD_FP32_STORAGE) ? NQ + 4 : NQ;
+    const size_t n = (size_t)h->p.nx * h->p.ny;
+    const double* src = state;
+    if (!on_device) {
+        int rc = ensure_staging(h, np * n * sizeof(double));
+        if (rc) return rc;
+        HIPCHK(hipMemcpyAsync(h->staging, state, np * n * sizeof(double), hipMemcpyHostToDevice, h->stream));
+        src = h->staging;
+    }
+    h->cur = 0;
+    dim3 grid = node_grid(h->p.nx, h->p.ny), block(BX, BY);
+    if (h->p.precision == MRTFD_FP32_STORAGE)
+        hipLaunchKernelGGL((k_scatter_state<float>), grid, block, 0, h->stream, (float*)h->buf[0], src, h->args);
+    else
+        hipLaunchKernelGGL((k_scatter_state<double>), grid, block, 0, h->stream, (double*)h->buf[0], src, h->args);
     HIPCHK(hipGetLastError());
     int rc = refill(h);
     if (rc) return rc;

@@ -62,6 +62,12 @@ struct StepArgs {
     long plane;                 // element stride between planes
     long elems;                 // elements of a state buffer
     long org;                   // element offset of node (0, 0) inside a plane
+    // FP32 storage only: the conserved moments (rho, j_x, j_y, e) of every
+    // node in FP64, in four planes beside the populations (offsets in
+    // doubles from the start of the buffer; 0 in FP64 storage)
+    long corg;                  // node (0, 0) of conserved plane 0
+    long cpitch;                // stride between rows
+    long cplane;                // stride between the four planes
     int x0, x1, y0, y1;         // evolved node range [x0, x1) x [y0, y1)
     int ntx, nty;               // step-kernel tiles along x and y
     int per_xcd;                // tiles per XCD slot (grid = 8 * per_xcd blocks)
@@ -134,6 +140,17 @@ template <class P>
 __host__ __device__ __forceinline__ double dot4(P r, const double* v)
 {
     return fma(r[0], v[0], fma(r[1], v[1], fma(r[2], v[2], r[3] * v[3])));
+}
+
+// The conserved moments (m_1..m_4: rho, j_x, j_y, e) from the angular sums,
+// formed exactly as moments() forms them.
+template <class BT>
+__host__ __device__ __forceinline__ void cons_of(const BT& B, const Sums& a, double* c)
+{
+    c[0] = (a.S[0] + a.S[1]) + (a.S[2] + a.S[3]);
+    c[1] = dot4(B.FX[0], a.X);
+    c[2] = dot4(B.FX[0], a.Y);
+    c[3] = dot4(B.F0[1], a.S);
 }
 
 // fhat = M f from the angular sums (all 16 moments).
@@ -232,6 +249,40 @@ __host__ __device__ __forceinline__ void inverse_full(const BT& B, const double*
     group_unsums<3>(S[3], X[3], Y[3], D[3], v + 12);
 }
 
+// v = M^-1 w for a moment vector whose only non-zero entries are the
+// conserved ones w_1..w_4 (d[0..3]).
+template <class BT>
+__host__ __device__ __forceinline__ void inverse_cons(const BT& B, const double* d, double* v)
+{
+    double S[4], X[4], Y[4], D[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        S[g] = fma(B.I0[g][0], d[0], B.I0[g][1] * d[3]);
+        X[g] = B.IX[g][0] * d[1];
+        Y[g] = B.IX[g][0] * d[2];
+    }
+    group_unsums<0>(S[0], X[0], Y[0], D[0], v + 0);
+    group_unsums<1>(S[1], X[1], Y[1], D[1], v + 4);
+    group_unsums<2>(S[2], X[2], Y[2], D[2], v + 8);
+    group_unsums<3>(S[3], X[3], Y[3], D[3], v + 12);
+}
+
+// FP32 storage keeps, beside the populations f~ rounded to FP32, the
+// conserved moments c of the FP64 populations they were rounded from.  The
+// node stands for f = f~ + M^-1 (c - M f~)_{1..4}: the rounded populations
+// with their conserved moments put back to c (their other moments unchanged).
+template <class BT>
+__host__ __device__ __forceinline__ void resync(const BT& B, const double* ft, const double* c, double* f)
+{
+    double m[4], d[4], v[NQ];
+    cons_of(B, all_sums(ft), m);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) d[k] = c[k] - m[k];
+    inverse_cons(B, d, v);
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) f[i] = ft[i] + v[i];
+}
+
 // f^eq in velocity space from primitive variables (rho, u, T).
 template <class BT>
 __device__ __forceinline__ void feq_velocity(const BT& B, double b, double rho, double ux,
@@ -261,15 +312,33 @@ __device__ __forceinline__ void macro_of(const BT& B, double inv_b, const double
     T = P * ir;
 }
 
+// rho, u, T from the conserved moments c = (rho, j_x, j_y, e).
+__device__ __forceinline__ void macro_of_cons(double inv_b, const double* c, double& rho, double& ux, double& uy,
+                                              double& T)
+{
+    rho = c[0];
+    double ir = 1.0 / rho;
+    ux = c[1] * ir;
+    uy = c[2] * ir;
+    double P = (c[3] - rho * (ux * ux + uy * uy)) * inv_b;
+    T = P * ir;
+}
+
+// Velocity from rho and j (neighbour ring of the correction).
+__device__ __forceinline__ void velocity_of_cons(double rho, double jx, double jy, double& ux, double& uy)
+{
+    double ir = 1.0 / rho;
+    ux = jx * ir;
+    uy = jy * ir;
+}
+
 // Density and velocity only (neighbour ring of the correction).
 template <class BT>
 __device__ __forceinline__ void velocity_of(const BT& B, const double* f, double& ux, double& uy)
 {
     Sums a = all_sums(f);
     double rho = (a.S[0] + a.S[1]) + (a.S[2] + a.S[3]);
-    double ir = 1.0 / rho;
-    ux = dot4(B.FX[0], a.X) * ir;
-    uy = dot4(B.FX[0], a.Y) * ir;
+    velocity_of_cons(rho, dot4(B.FX[0], a.X), dot4(B.FX[0], a.Y), ux, uy);
 }
 
 // ---------------------------------------------------------------------------
@@ -330,12 +399,19 @@ __device__ __forceinline__ R acc_start(double c)
     if constexpr (sizeof(T) == 8) return c;
     else return R(0);
 }
+// (returned in FP64 before the store rounds it to T: FP32 storage also
+// keeps the conserved moments of these FP64 values)
 template <typename T, typename R>
-__device__ __forceinline__ T new_value(R f0, R acc, double c)
+__device__ __forceinline__ double new_value(R f0, R acc, double c)
 {
     if constexpr (sizeof(T) == 8) return f0 + acc;
-    else return (T)((double)f0 + (double)acc + c);
+    else return (double)f0 + (double)acc + c;
 }
+
+// Whether a storage type keeps the conserved moments in FP64 planes beside
+// its populations (FP32 storage).
+template <typename T>
+constexpr bool keeps_cons() { return sizeof(T) == 4; }
 
 // Courant number and (1 - nu) / 2 of group g along x (AX = 0) or y (AX = 1)
 // in the convection precision R.

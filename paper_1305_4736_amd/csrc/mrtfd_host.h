@@ -36,13 +36,12 @@ inline int fail(int code, const char* fmt, ...)
             return fail(MRTFD_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));      \
     } while (0)
 
-// State layout: 16 planes of (ny + 4) padded rows.  With ROW_INTERLEAVED the
-// 16 planes of one row are adjacent (row stride 16 pitch, plane stride
-// pitch), otherwise each plane is contiguous (row stride pitch, plane stride
-// (ny + 4) pitch).  Kernels only use the two strides and the origin.
-#ifndef MRTFD_ROW_INTERLEAVED
-#define MRTFD_ROW_INTERLEAVED 1
-#endif
+// State layout: 16 planes of (ny + 4) padded rows, interleaved by row: the
+// 16 rows (one per plane) of grid row y are adjacent (row stride 16 pitch,
+// plane stride pitch).  FP32 storage follows each row with four FP64 planes
+// of the conserved moments (rho, j_x, j_y, e) of its nodes, pitch doubles
+// each, so a row holds 16 pitch floats and then 4 pitch doubles.  Kernels
+// only use the strides and the origins.
 struct Layout {
     size_t esize;
     long pitch;     // elements of one padded row of one plane
@@ -51,27 +50,37 @@ struct Layout {
     long org;       // element offset of node (0, 0) in plane 0
     long elems;     // elements of a buffer
     size_t buf_bytes;
+    long corg, cpitch, cplane;   // FP32 storage: conserved planes, in doubles (0 otherwise)
 };
 
 inline Layout layout_of(const mrtfd_params& p)
 {
     Layout L;
-    L.esize = (p.precision == MRTFD_FP32_STORAGE) ? 4 : 8;
+    const bool cons = p.precision == MRTFD_FP32_STORAGE;
+    L.esize = cons ? 4 : 8;
     const long line = 128 / (long)L.esize;   // elements per 128-byte line
     const long xoff = line;                  // x = 0 starts a line; ghosts sit before it
     L.pitch = ((xoff + p.nx + HALO + line - 1) / line) * line;
     const long rows = (long)(p.ny + 2 * HALO);
-    L.row = MRTFD_ROW_INTERLEAVED ? NQ * L.pitch : L.pitch;
-    L.plane = MRTFD_ROW_INTERLEAVED ? L.pitch : rows * L.pitch;
+    // a conserved plane's row (pitch doubles) is 2 pitch floats
+    L.row = NQ * L.pitch + (cons ? 4 * 2 * L.pitch : 0);
+    L.plane = L.pitch;
     L.org = (long)HALO * L.row + xoff;
-    L.elems = (long)NQ * rows * L.pitch;
+    L.elems = rows * L.row;
     L.buf_bytes = (size_t)L.elems * L.esize;
+    if (cons) {
+        L.cpitch = L.row / 2;
+        L.cplane = L.pitch;
+        L.corg = (long)HALO * L.cpitch + NQ * L.pitch / 2 + 32;   // x = 0 at a 256-byte offset of its row
+    } else {
+        L.corg = L.cpitch = L.cplane = 0;
+    }
     return L;
 }
 
 // Largest element offset inside one plane's addressing (kernels form the
 // offset of a node within its plane in 32-bit integers).
-inline long plane_span(const Layout& L) { return MRTFD_ROW_INTERLEAVED ? L.elems : L.plane; }
+inline long plane_span(const Layout& L) { return L.elems; }
 
 inline int validate(const mrtfd_params* p)
 {
@@ -157,6 +166,9 @@ inline StepArgs make_args(const mrtfd_params& p, const Layout& L, const Blocks& 
     a.plane = L.plane;
     a.org = L.org;
     a.elems = L.elems;
+    a.corg = L.corg;
+    a.cpitch = L.cpitch;
+    a.cplane = L.cplane;
     a.x0 = (p.bc[0].kind == BC_WALL);
     a.x1 = p.nx - (p.bc[1].kind == BC_WALL);
     a.y0 = (p.bc[2].kind == BC_WALL);

@@ -61,6 +61,76 @@ __device__ __forceinline__ void load16(const T* __restrict__ f, const StepArgs& 
     for (int i = 0; i < NQ; ++i) out[i] = (double)f[i * a.plane + n];
 }
 
+// Offset (in doubles) of node (x, y) in conserved plane 0 (FP32 storage).
+__device__ __forceinline__ long cnode(const StepArgs& a, int x, int y)
+{
+    return a.corg + (long)y * a.cpitch + x;
+}
+
+// Conserved moments (rho, j_x, j_y, e) of node (x, y): the stored FP64
+// planes in FP32 storage, the sums of the populations in FP64 storage.
+template <typename T>
+__device__ __forceinline__ void cons_node(const T* __restrict__ f, const StepArgs& a, int x, int y, double* c)
+{
+    if constexpr (keeps_cons<T>()) {
+        const double* cp = (const double*)f + cnode(a, x, y);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) c[k] = cp[k * a.cplane];
+    } else {
+        double v[NQ];
+        load16(f, a, node(a, x, y), v);
+        cons_of(*a.Bp, all_sums(v), c);
+    }
+}
+
+// The FP64 populations node (x, y) stands for (FP32 storage: the rounded
+// populations put back onto their conserved moments).
+template <typename T>
+__device__ __forceinline__ void load_node(const T* __restrict__ f, const StepArgs& a, int x, int y, double* out)
+{
+    if constexpr (keeps_cons<T>()) {
+        double ft[NQ], c[4];
+        load16(f, a, node(a, x, y), ft);
+        cons_node(f, a, x, y, c);
+        resync(*a.Bp, ft, c, out);
+    } else {
+        load16(f, a, node(a, x, y), out);
+    }
+}
+
+// Store FP64 populations v at node (x, y): rounded to T, and in FP32
+// storage their conserved moments beside them.
+template <typename T>
+__device__ __forceinline__ void store_node(T* __restrict__ f, const StepArgs& a, int x, int y, const double* v)
+{
+    const long n = node(a, x, y);
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) f[i * a.plane + n] = (T)v[i];
+    if constexpr (keeps_cons<T>()) {
+        double c[4];
+        cons_of(*a.Bp, all_sums(v), c);
+        double* cp = (double*)f + cnode(a, x, y);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) cp[k * a.cplane] = c[k];
+    }
+}
+
+// Copy node (xs, ys) to (xd, yd) bit for bit (populations and, in FP32
+// storage, conserved moments).
+template <typename T>
+__device__ __forceinline__ void copy_node(T* __restrict__ f, const StepArgs& a, int xs, int ys, int xd, int yd)
+{
+    const long ns = node(a, xs, ys), nd = node(a, xd, yd);
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) f[i * a.plane + nd] = f[i * a.plane + ns];
+    if constexpr (keeps_cons<T>()) {
+        double* cp = (double*)f;
+        const long cs = cnode(a, xs, ys), cd = cnode(a, xd, yd);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) cp[k * a.cplane + cd] = cp[k * a.cplane + cs];
+    }
+}
+
 
 // Non-equilibrium extrapolation wall from the fluid node next to it (f1):
 // fw[i] is the wall node's population i; its ghosts k = 1, 2 beyond the
@@ -79,17 +149,28 @@ __device__ __forceinline__ void wall_values(const AT& a, const BT& B, const doub
     for (int i = 0; i < NQ; ++i) fw[i] = ew[i] + (f1[i] - e1[i]);
 }
 
-// The wall node n_w and its two ghosts n_w + step, n_w + 2 step.
-template <typename T>
-__device__ void wall_fill(const StepArgs& a, T* __restrict__ f, const double* f1, int side, long nw, long step)
+// Ghost k (1 or 2) beyond a wall: the line through f_1 and the wall node
+// continued, (k + 1) f_w - k f_1 (one expression per k, shared by every
+// kernel so that all of them round it alike).
+__device__ __forceinline__ double wall_ghost(double fw, double f1, int k)
 {
-    double fw[NQ];
+    return (k == 1) ? 2.0 * fw - f1 : 3.0 * fw - 2.0 * f1;
+}
+
+// The wall node (xw, yw) and its two ghosts one and two nodes further out
+// along (sx, sy), from the populations f1 of the fluid node next to it.
+template <typename T>
+__device__ void wall_fill(const StepArgs& a, T* __restrict__ f, const double* f1, int side, int xw, int yw, int sx,
+                          int sy)
+{
+    double fw[NQ], g[NQ];
     wall_values(a, *a.Bp, f1, side, fw);
+    store_node(f, a, xw, yw, fw);
 #pragma unroll
-    for (int i = 0; i < NQ; ++i) {
-        f[i * a.plane + nw] = (T)fw[i];
-        f[i * a.plane + nw + step] = (T)(2.0 * fw[i] - f1[i]);
-        f[i * a.plane + nw + 2 * step] = (T)(3.0 * fw[i] - 2.0 * f1[i]);
+    for (int k = 1; k <= 2; ++k) {
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) g[i] = wall_ghost(fw[i], f1[i], k);
+        store_node(f, a, xw + k * sx, yw + k * sy, g);
     }
 }
 
@@ -98,16 +179,21 @@ __device__ void wall_fill(const StepArgs& a, T* __restrict__ f, const double* f1
 
 // Relaxed residual of the non-conserved moments, mapped back to velocity
 // space and scaled by -dt (the collision term of the update).
-template <class AT, class BT>
+//
+// CONS (FP32 storage): dc holds the node's stored conserved moments minus
+// those of its rounded populations; they enter the increment unscaled, so
+// that the new populations carry the stored conserved moments (the rounded
+// ones are put back onto them before the update).
+template <bool CONS, class AT, class BT>
 __device__ __forceinline__ void collision(const AT& a, const BT& B, const double* m, double rho, double ux, double uy,
                                           double P, bool corr, double dxux, double dxuy, double dyux,
-                                          double dyuy, double* coll)
+                                          double dyuy, const double* dc, double* coll)
 {
     double eq[NQ];
     equilibria(rho, ux, uy, P, m[3], a.b, eq);
     double w[NQ];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) w[k] = 0.0;
+    for (int k = 0; k < 4; ++k) w[k] = CONS ? dc[k] : 0.0;
 #pragma unroll
     for (int k = 4; k < NQ; ++k) w[k] = a.rdt[k] * (m[k] - eq[k]);
     if (corr) {
@@ -117,15 +203,32 @@ __device__ __forceinline__ void collision(const AT& a, const BT& B, const double
         w[7] += a.c8dt * P * (ux * (4.0 * dxux - div4b) + uy * shear2);
         w[8] += a.c9dt * P * (ux * shear2 + uy * (4.0 * dyuy - div4b));
     }
-    inverse_nc(B, w, coll);
+    if constexpr (CONS) inverse_full(B, w, coll);
+    else inverse_nc(B, w, coll);
+}
+
+// Moments of a node from its stored populations ft: all 16 from the
+// populations, then in FP32 storage the conserved ones replaced by the
+// stored c, with dc = c - (those of ft).
+template <typename T, class BT>
+__device__ __forceinline__ void node_moments(const BT& B, const double* ft, const double* c, double* m, double* dc)
+{
+    moments(B, all_sums(ft), m);
+    if constexpr (keeps_cons<T>()) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            dc[k] = c[k] - m[k];
+            m[k] = c[k];
+        }
+    }
 }
 
 // Periodic and outflow ghost images owned by node (x, y): up to 4 along x
 // and 4 along y (a single-node axis wraps onto all four ghosts).  Returns the
-// count; offs[] are element offsets relative to the node.  Wall nodes and
-// their ghosts are filled afterwards by k_fill (walls only).
+// count; (ox[q], oy[q]) are the images' offsets from the node.  Wall nodes
+// and their ghosts are filled afterwards by k_fill (walls only).
 template <class AT>
-__device__ __forceinline__ int image_offsets(const AT& a, int x, int y, int* offs)
+__device__ __forceinline__ int image_offsets(const AT& a, int x, int y, int* ox, int* oy)
 {
     int n = 0;
     if (a.bc[0] == BC_PERIODIC) {
@@ -133,36 +236,41 @@ __device__ __forceinline__ int image_offsets(const AT& a, int x, int y, int* off
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int xg = (q < 2) ? (q - 2) : (a.nx + q - 2);
-                if ((((xg % a.nx) + a.nx) % a.nx) == x) offs[n++] = xg - x;
+                if ((((xg % a.nx) + a.nx) % a.nx) == x) {
+                    ox[n] = xg - x;
+                    oy[n++] = 0;
+                }
             }
         }
     } else {
         if (a.bc[0] == BC_OUTFLOW && x == 0) {
-            offs[n++] = -1;
-            offs[n++] = -2;
+            ox[n] = -1; oy[n++] = 0;
+            ox[n] = -2; oy[n++] = 0;
         }
         if (a.bc[1] == BC_OUTFLOW && x == a.nx - 1) {
-            offs[n++] = 1;
-            offs[n++] = 2;
+            ox[n] = 1; oy[n++] = 0;
+            ox[n] = 2; oy[n++] = 0;
         }
     }
-    const int pitch = (int)a.pitch;
     if (a.bc[2] == BC_PERIODIC) {
         if (y < 2 || y >= a.ny - 2) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int yg = (q < 2) ? (q - 2) : (a.ny + q - 2);
-                if ((((yg % a.ny) + a.ny) % a.ny) == y) offs[n++] = (yg - y) * pitch;
+                if ((((yg % a.ny) + a.ny) % a.ny) == y) {
+                    ox[n] = 0;
+                    oy[n++] = yg - y;
+                }
             }
         }
     } else {
         if (a.bc[2] == BC_OUTFLOW && y == 0) {
-            offs[n++] = -pitch;
-            offs[n++] = -2 * pitch;
+            ox[n] = 0; oy[n++] = -1;
+            ox[n] = 0; oy[n++] = -2;
         }
         if (a.bc[3] == BC_OUTFLOW && y == a.ny - 1) {
-            offs[n++] = pitch;
-            offs[n++] = 2 * pitch;
+            ox[n] = 0; oy[n++] = 1;
+            ox[n] = 0; oy[n++] = 2;
         }
     }
     return n;
@@ -249,13 +357,15 @@ __device__ __forceinline__ void step_tile(const T* __restrict__ fin, T* __restri
 
     // ---- moments of the own node, velocity of the own node and of the ring
     const int c0 = (ty + HY) * TW + tx + 2;          // own position in a staged plane
-    double m[NQ], rho = 1.0, ux = 0.0, uy = 0.0, P = 1.0;
+    double m[NQ], dc[4], rho = 1.0, ux = 0.0, uy = 0.0, P = 1.0;
     {
-        double f[NQ];
+        double f[NQ], c[4] = {1.0, 0.0, 0.0, 1.0};
 #pragma unroll
         for (int i = 0; i < NQ; ++i) f[i] = (double)tile[i * TN + c0];
-        Sums sm = all_sums(f);
-        moments(*a.Bp, sm, m);
+        // (FP32 storage: the stored conserved moments, on the grid and its
+        // ghosts; threads beyond them keep a placeholder nobody reads)
+        if (keeps_cons<T>() && x >= -2 && x <= a.nx + 1 && y >= -2 && y <= a.ny + 1) cons_node(fin, a, x, y, c);
+        node_moments<T>(*a.Bp, f, c, m, dc);
         rho = m[0];
         const double ir = 1.0 / rho;
         ux = m[1] * ir;
@@ -280,12 +390,21 @@ __device__ __forceinline__ void step_tile(const T* __restrict__ fin, T* __restri
             } else {
                 lx = TXW; ly = q - 2 * RY - BYR;
             }
-            double g[NQ], vx = 0.0, vy = 0.0;
+            double vx = 0.0, vy = 0.0;
             const int cr = (ly + HY) * TW + lx + 2;
-#pragma unroll
-            for (int i = 0; i < NQ; ++i) g[i] = (double)tile[i * TN + cr];
             const int rx = xb + lx, ry = yb + ly;
-            if (rx >= a.x0 - 1 && rx <= a.x1 && ry >= a.y0 - 1 && ry <= a.y1) velocity_of(*a.Bp, g, vx, vy);
+            if (rx >= a.x0 - 1 && rx <= a.x1 && ry >= a.y0 - 1 && ry <= a.y1) {
+                if constexpr (keeps_cons<T>()) {
+                    double c[4];
+                    cons_node(fin, a, rx, ry, c);
+                    velocity_of_cons(c[0], c[1], c[2], vx, vy);
+                } else {
+                    double g[NQ];
+#pragma unroll
+                    for (int i = 0; i < NQ; ++i) g[i] = (double)tile[i * TN + cr];
+                    velocity_of(*a.Bp, g, vx, vy);
+                }
+            }
             sux[(ly + 1) * UW + lx + 1] = vx;
             suy[(ly + 1) * UW + lx + 1] = vy;
         }
@@ -301,10 +420,11 @@ __device__ __forceinline__ void step_tile(const T* __restrict__ fin, T* __restri
     if (!active) return;
     if (!(rho > 0.0 && P > 0.0)) atomicOr(a.flag, 1);
     double coll[NQ];
-    collision(a, *a.Bp, m, rho, ux, uy, P, corr, dxux, dxuy, dyux, dyuy, coll);
+    collision<keeps_cons<T>()>(a, *a.Bp, m, rho, ux, uy, P, corr, dxux, dxuy, dyux, dyuy, dc, coll);
 
     // ---- limited fluxes and the update, plane by plane
     using R = conv_t<T>;   // convection precision
+    double vd[NQ];         // new populations in FP64 (FP32 storage keeps their conserved moments)
 #pragma unroll
     for (int i = 0; i < NQ; ++i) {
         const T* tb = tile + i * TN;
@@ -319,19 +439,21 @@ __device__ __forceinline__ void step_tile(const T* __restrict__ fin, T* __restri
             const int sy = sgy(i) * TW;
             acc = conv1<LIM, R>(acc, tb[c0 - 2 * sy], tb[c0 - sy], f0, tb[c0 + sy], nu_of<R, 1>(a, g), c_of<R, 1>(a, g));
         }
-        fout[(long)i * a.plane + n0] = new_value<T, R>(f0, acc, coll[i]);
+        vd[i] = new_value<T, R>(f0, acc, coll[i]);
+        fout[(long)i * a.plane + n0] = (T)vd[i];
+    }
+    if constexpr (keeps_cons<T>()) {
+        double c[4];
+        cons_of(*a.Bp, all_sums(vd), c);
+        double* cp = (double*)fout + cnode(a, x, y);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) cp[k * a.cplane] = c[k];
     }
 
-    int offs[8];
-    const int nimg = image_offsets(a, x, y, offs);
-    if (nimg > 0) {
-        // copy this thread's own new values (same thread, same addresses)
-        for (int i = 0; i < NQ; ++i) {
-            T* pl = fout + (long)i * a.plane;
-            const T v = pl[n0];
-            for (int q = 0; q < nimg; ++q) pl[n0 + offs[q]] = v;
-        }
-    }
+    int ox[8], oy[8];
+    const int nimg = image_offsets(a, x, y, ox, oy);
+    // copy this thread's own new values (same thread, same addresses)
+    for (int q = 0; q < nimg; ++q) copy_node(fout, a, x, y, x + ox[q], y + oy[q]);
 }
 
 // Single instance: one block per tile.  Blocks are assigned round-robin to
@@ -360,9 +482,7 @@ __global__ void k_init(T* __restrict__ f, const double* __restrict__ rho, const 
     const long d = (long)y * a.nx + x;
     double fe[NQ];
     feq_velocity(*a.Bp, a.b, rho[d], ux[d], uy[d], Tf[d], fe);
-    const long n = node(a, x, y);
-#pragma unroll
-    for (int i = 0; i < NQ; ++i) f[i * a.plane + n] = (T)fe[i];
+    store_node(f, a, x, y, fe);
 }
 
 // Ghost fill of one side line: thread index t covers line t / 2 of axis
@@ -376,27 +496,32 @@ __device__ void fill_line(T* __restrict__ f, const StepArgs& a, int axis, int t,
     const int line = t >> 1;
     const int side = 2 * axis + (side_lo ? 0 : 1);
     const int n = (axis == 0) ? a.nx : a.ny;
-    const long stride = (axis == 0) ? 1 : a.pitch;
-    const long base = (axis == 0) ? node(a, 0, line) : node(a, line, 0);   // node at coordinate 0
     const int kind = a.bc[side];
     if (walls_only && kind != BC_WALL) return;
-    double v[NQ];
+    // coordinate c along the axis -> node of this line
+    auto px = [&](int c) { return (axis == 0) ? c : line; };
+    auto py = [&](int c) { return (axis == 0) ? line : c; };
+    const int out = side_lo ? -1 : 1;
     if (kind == BC_WALL) {
         const int c1 = side_lo ? 1 : n - 2, cw = side_lo ? 0 : n - 1;
-        load16(f, a, base + c1 * stride, v);
-        wall_fill(a, f, v, side, base + cw * stride, side_lo ? -stride : stride);
+        double v[NQ];
+        load_node(f, a, px(c1), py(c1), v);
+        wall_fill(a, f, v, side, px(cw), py(cw), (axis == 0) ? out : 0, (axis == 0) ? 0 : out);
         return;
     }
+    double v[NQ];
     if (kind == BC_EQUIL) {
         const double* st = a.side[side];
         feq_velocity(*a.Bp, a.b, st[0], st[1], st[2], st[3], v);
     }
     for (int k = 1; k <= 2; ++k) {
         const int cg = side_lo ? -k : n - 1 + k;
-        if (kind == BC_PERIODIC) load16(f, a, base + (long)(((cg % n) + n) % n) * stride, v);
-        else if (kind == BC_OUTFLOW) load16(f, a, base + (long)(side_lo ? 0 : n - 1) * stride, v);
-#pragma unroll
-        for (int i = 0; i < NQ; ++i) f[i * a.plane + base + (long)cg * stride] = (T)v[i];
+        if (kind == BC_EQUIL) {
+            store_node(f, a, px(cg), py(cg), v);
+        } else {
+            const int cs = (kind == BC_PERIODIC) ? ((cg % n) + n) % n : (side_lo ? 0 : n - 1);
+            copy_node(f, a, px(cs), py(cs), px(cg), py(cg));
+        }
     }
 }
 
@@ -417,9 +542,16 @@ __global__ void k_macros(const T* __restrict__ f, double* rho, double* ux, doubl
 {
     const int x = blockIdx.x * BX + threadIdx.x, y = blockIdx.y * BY + threadIdx.y;
     if (x >= a.nx || y >= a.ny) return;
-    double v[NQ], r, vx, vy, t;
-    load16(f, a, node(a, x, y), v);
-    macro_of(*a.Bp, a.inv_b, v, r, vx, vy, t);
+    double r, vx, vy, t;
+    if constexpr (keeps_cons<T>()) {
+        double c[4];
+        cons_node(f, a, x, y, c);
+        macro_of_cons(a.inv_b, c, r, vx, vy, t);
+    } else {
+        double v[NQ];
+        load16(f, a, node(a, x, y), v);
+        macro_of(*a.Bp, a.inv_b, v, r, vx, vy, t);
+    }
     const long d = (long)y * a.nx + x;
     if (rho) rho[d] = r;
     if (ux) ux[d] = vx;
@@ -434,10 +566,10 @@ __global__ void k_noneq(const T* __restrict__ f, int star, double* __restrict__ 
 {
     const int x = blockIdx.x * BX + threadIdx.x, y = blockIdx.y * BY + threadIdx.y;
     if (x >= a.nx || y >= a.ny) return;
-    double v[NQ], m[NQ], eq[NQ], dl[NQ];
+    double v[NQ], m[NQ], eq[NQ], dl[NQ], c[4], dc[4];
     load16(f, a, node(a, x, y), v);
-    Sums sm = all_sums(v);
-    moments(*a.Bp, sm, m);
+    if constexpr (keeps_cons<T>()) cons_node(f, a, x, y, c);
+    node_moments<T>(*a.Bp, v, c, m, dc);
     const double rho = m[0], ir = 1.0 / rho, ux = m[1] * ir, uy = m[2] * ir;
     const double P = (m[3] - rho * (ux * ux + uy * uy)) * a.inv_b;
     equilibria(rho, ux, uy, P, m[3], a.b, eq);
@@ -487,9 +619,11 @@ __global__ void k_gather(const T* __restrict__ f, double* __restrict__ out, Step
 {
     const int x = blockIdx.x * BX + threadIdx.x, y = blockIdx.y * BY + threadIdx.y;
     if (x >= a.nx || y >= a.ny) return;
-    const long plane = (long)a.nx * a.ny, d = (long)y * a.nx + x, n = node(a, x, y);
+    const long plane = (long)a.nx * a.ny, d = (long)y * a.nx + x;
+    double v[NQ];
+    load_node(f, a, x, y, v);
 #pragma unroll
-    for (int i = 0; i < NQ; ++i) out[i * plane + d] = (double)f[i * a.plane + n];
+    for (int i = 0; i < NQ; ++i) out[i * plane + d] = v[i];
 }
 
 template <typename T>
@@ -497,11 +631,48 @@ __global__ void k_scatter(T* __restrict__ f, const double* __restrict__ in, Step
 {
     const int x = blockIdx.x * BX + threadIdx.x, y = blockIdx.y * BY + threadIdx.y;
     if (x >= a.nx || y >= a.ny) return;
+    const long plane = (long)a.nx * a.ny, d = (long)y * a.nx + x;
+    double v[NQ];
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) v[i] = in[i * plane + d];
+    store_node(f, a, x, y, v);
+}
+
+
+// The stored state of every grid node as doubles, exactly: the 16 stored
+// populations, then (FP32 storage) the 4 conserved moments; (nplanes, ny, nx).
+template <typename T>
+__device__ __forceinline__ int state_planes() { return keeps_cons<T>() ? NQ + 4 : NQ; }
+
+template <typename T>
+__global__ void k_gather_state(const T* __restrict__ f, double* __restrict__ out, StepArgs a)
+{
+    const int x = blockIdx.x * BX + threadIdx.x, y = blockIdx.y * BY + threadIdx.y;
+    if (x >= a.nx || y >= a.ny) return;
+    const long plane = (long)a.nx * a.ny, d = (long)y * a.nx + x, n = node(a, x, y);
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) out[i * plane + d] = (double)f[i * a.plane + n];
+    if constexpr (keeps_cons<T>()) {
+        const double* cp = (const double*)f + cnode(a, x, y);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) out[(NQ + k) * plane + d] = cp[k * a.cplane];
+    }
+}
+
+template <typename T>
+__global__ void k_scatter_state(T* __restrict__ f, const double* __restrict__ in, StepArgs a)
+{
+    const int x = blockIdx.x * BX + threadIdx.x, y = blockIdx.y * BY + threadIdx.y;
+    if (x >= a.nx || y >= a.ny) return;
     const long plane = (long)a.nx * a.ny, d = (long)y * a.nx + x, n = node(a, x, y);
 #pragma unroll
     for (int i = 0; i < NQ; ++i) f[i * a.plane + n] = (T)in[i * plane + d];
+    if constexpr (keeps_cons<T>()) {
+        double* cp = (double*)f + cnode(a, x, y);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) cp[k * a.cplane] = in[(NQ + k) * plane + d];
+    }
 }
-
 
 // ---------------------------------------------------------------------------
 // Batched form: many independent instances advance in one persistent launch

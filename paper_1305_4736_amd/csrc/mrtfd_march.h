@@ -134,6 +134,11 @@ __device__ __forceinline__ void buf_store(float v, __amdgpu_buffer_rsrc_t r, uns
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)voff, (int)soff, MARCH_STORE_AUX);
 }
 
+// Per-lane byte offset of a conserved-moment plane (FP64) from that of a
+// population plane (FP32 storage, 4-byte elements): twice as far; NO_STORE
+// stays NO_STORE.
+__device__ __forceinline__ unsigned cons_off(unsigned voff) { return (voff == NO_STORE) ? NO_STORE : 2u * voff; }
+
 // Coordinate c in [-2, n + 1] of an axis with n nodes, mapped to the node
 // that holds its value: periodic sides wrap, outflow sides repeat the last
 // node, equilibrium and wall sides keep their stored ghosts.
@@ -187,34 +192,61 @@ constexpr int PRING = 4;          // rows held by the ring of a pair
 constexpr int POUT = MW - 8;      // output columns of a pair's strip
 
 // The ring: row y of the first step's result lives in slot (y + 4) mod 4
-// (y >= -2), lane l of the strip at [slot][plane][l].
+// (y >= -2), lane l of the strip at [slot][plane][l]; FP32 storage also
+// passes each row's FP64 conserved moments, at [slot][k][l].
 template <typename T>
 struct PairRing {
     T v[PRING][NQ][MW];
+};
+template <>
+struct PairRing<float> {
+    float v[PRING][NQ][MW];
+    double c[PRING][4][MW];
 };
 
 // Wall rows of step n + 1 in a pair's ring, lane `lane`: the first step's
 // row c1 next to the wall gives, by the same arithmetic as the refill after
 // a one-step launch, the wall node's row w (kmin = 0) and its first ghost
 // row w + out (kmax = 1; out = -1 on the low side, +1 on the high side).
+// A row of FP64 populations v written to ring slot `sl` at lane `lane`
+// (rounded to T; FP32 storage also writes their conserved moments).
+template <typename T>
+__device__ __forceinline__ void ring_put(CArgs& a, PairRing<T>* ring, int sl, int lane, const double* v)
+{
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) ring->v[sl][i][lane] = (T)v[i];
+    if constexpr (keeps_cons<T>()) {
+        double c[4];
+        cons_of(blocks_of(a), all_sums(v), c);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) ring->c[sl][k][lane] = c[k];
+    }
+}
+
 template <typename T>
 __device__ __forceinline__ void ring_wall(CArgs& a, PairRing<T>* ring, int lane, int side, int c1, int w, int out,
                                           int kmin, int kmax)
 {
-    const T(*src)[MW] = ring->v[(c1 + 4) & (PRING - 1)];
+    const int s1 = (c1 + 4) & (PRING - 1);
     double f1[NQ], fw[NQ];
+    if constexpr (keeps_cons<T>()) {
+        double ft[NQ], c[4];
 #pragma unroll
-    for (int i = 0; i < NQ; ++i) f1[i] = (double)src[i][lane];
-    wall_values(a, blocks_of(a), f1, side, fw);
-    if (kmin == 0) {
-        T(*dst)[MW] = ring->v[(w + 4) & (PRING - 1)];
+        for (int i = 0; i < NQ; ++i) ft[i] = (double)ring->v[s1][i][lane];
 #pragma unroll
-        for (int i = 0; i < NQ; ++i) dst[i][lane] = (T)fw[i];
+        for (int k = 0; k < 4; ++k) c[k] = ring->c[s1][k][lane];
+        resync(blocks_of(a), ft, c, f1);
+    } else {
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) f1[i] = (double)ring->v[s1][i][lane];
     }
+    wall_values(a, blocks_of(a), f1, side, fw);
+    if (kmin == 0) ring_put(a, ring, (w + 4) & (PRING - 1), lane, fw);
     if (kmax == 1) {
-        T(*dst)[MW] = ring->v[(w + out + 4) & (PRING - 1)];
+        double g[NQ];
 #pragma unroll
-        for (int i = 0; i < NQ; ++i) dst[i][lane] = (T)(2.0 * fw[i] - f1[i]);
+        for (int i = 0; i < NQ; ++i) g[i] = wall_ghost(fw[i], f1[i], 1);
+        ring_put(a, ring, (w + out + 4) & (PRING - 1), lane, g);
     }
 }
 
@@ -244,6 +276,7 @@ struct Marcher {
     bool pass;                        // ROLE_FIRST: an equilibrium ghost column (value passes through)
     bool chk;                         // ROLE_FIRST: an interior column this wavefront checks
     T W[4][NQ];                       // the window (see above)
+    double CW[4][4];                  // FP32 storage: conserved moments of each window row
     double U[4], V[4];                // velocity (u_x, u_y) of each window row
     R carry[NQ];                      // limited jump of the y face carried from the previous row
 
@@ -311,12 +344,45 @@ struct Marcher {
         for (int i = 0; i < NQ; ++i) dst[i] = buf_load(rin, vin, base + (unsigned)i * pb, (T*)nullptr);
     }
 
-    __device__ __forceinline__ static void velocity(const T (&src)[NQ], double& vx, double& vy, CArgs& a)
+    // FP32 storage: the conserved moments of row y, from the same source as load().
+    __device__ __forceinline__ void load_cons(double (&dst)[4], int y, CArgs& a) const
     {
-        double g[NQ];
+        if constexpr (keeps_cons<T>()) {
+            if (ROLE == ROLE_SECOND) {
+                const int ys = source_out(max(-2, min(y, a.ny + 1)), a.ny, a.bc[2], a.bc[3]);
+                const int sl = (ys + 4) & (PRING - 1);
 #pragma unroll
-        for (int i = 0; i < NQ; ++i) g[i] = (double)src[i];
-        velocity_of(blocks_of(a), g, vx, vy);
+                for (int k = 0; k < 4; ++k) dst[k] = ring->c[sl][k][lane];
+                return;
+            }
+            const int ys = (ROLE == ROLE_FIRST) ? source_ext(y, a.ny, a.bc[2], a.bc[3])
+                                                : source_of(max(-2, min(y, a.ny + 1)), a.ny, a.bc[2], a.bc[3]);
+            const unsigned base = (unsigned)((a.corg - 2 + (long)ys * a.cpitch) * 8L);
+            const unsigned pb = (unsigned)(a.cplane * 8L);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) dst[k] = buf_load(rin, 2u * vin, base + (unsigned)k * pb, (double*)nullptr);
+        }
+    }
+
+    // A whole window row: populations and (FP32 storage) conserved moments.
+    __device__ __forceinline__ void load_row(int s, int y, CArgs& a)
+    {
+        load(W[s], y, a);
+        load_cons(CW[s], y, a);
+    }
+
+    // Velocity of window row s: from its populations, or in FP32 storage
+    // from its stored conserved moments.
+    __device__ __forceinline__ void velocity(int s, CArgs& a)
+    {
+        if constexpr (keeps_cons<T>()) {
+            velocity_of_cons(CW[s][0], CW[s][1], CW[s][2], U[s], V[s]);
+        } else {
+            double g[NQ];
+#pragma unroll
+            for (int i = 0; i < NQ; ++i) g[i] = (double)W[s][i];
+            velocity_of(blocks_of(a), g, U[s], V[s]);
+        }
     }
 
     // Limited jump of the y face carried into the first output row j0 (the
@@ -340,7 +406,7 @@ struct Marcher {
 
     // New value of plane i at output row j, walked in phase PH.
     template <int PH>
-    __device__ __forceinline__ T plane_value(int i, const double* coll, CArgs& a)
+    __device__ __forceinline__ double plane_value(int i, const double* coll, CArgs& a)
     {
         const T(&fB)[NQ] = W[PH & 3];
         const T(&fC)[NQ] = W[(PH + 1) & 3];
@@ -383,16 +449,15 @@ struct Marcher {
     {
         constexpr int B = PH & 3, C = (PH + 1) & 3, D = (PH + 2) & 3, E = (PH + 3) & 3;
         CArgs& a = args();
-        load(W[E], j + 2 * DIR, a);
+        load_row(E, j + 2 * DIR, a);
 
         // moments, equilibria, correction and collision of row j
-        double m[NQ];
+        double m[NQ], dc[4];
         {
             double g[NQ];
 #pragma unroll
             for (int i = 0; i < NQ; ++i) g[i] = (double)W[C][i];
-            Sums sm = all_sums(g);
-            moments(blocks_of(a), sm, m);
+            node_moments<T>(blocks_of(a), g, CW[C], m, dc);
         }
         const double rho = m[0];
         const double vx = U[C], vy = V[C];
@@ -410,7 +475,7 @@ struct Marcher {
         const bool checked = (ROLE == ROLE_FIRST) ? (chk && j >= a.y0 && j < a.y1) : (vout != NO_STORE);
         if (checked && !(rho > 0.0 && P > 0.0)) atomicOr(a.flag, 1);
         double coll[NQ];
-        collision(a, blocks_of(a), m, rho, vx, vy, P, corr, dxux, dxuy, dyux, dyuy, coll);
+        collision<keeps_cons<T>()>(a, blocks_of(a), m, rho, vx, vy, P, corr, dxux, dxuy, dyux, dyuy, dc, coll);
 
         const unsigned base = (unsigned)((a.org - 2 + (long)j * a.pitch) * (long)sizeof(T));
         const unsigned pb = (unsigned)(a.plane * (long)sizeof(T));
@@ -420,18 +485,34 @@ struct Marcher {
                               ((j < 0 && a.bc[2] == BC_EQUIL) || (j >= a.ny && a.bc[3] == BC_EQUIL));
         const bool keep = (ROLE == ROLE_FIRST) &&
                           (pass || (j < 0 && a.bc[2] == BC_EQUIL) || (j >= a.ny && a.bc[3] == BC_EQUIL));
-        T(*dst)[MW] = (ROLE == ROLE_FIRST) ? ring->v[(j + 4) & (PRING - 1)] : nullptr;
+        const int rs = (j + 4) & (PRING - 1);
+        T(*dst)[MW] = (ROLE == ROLE_FIRST) ? ring->v[rs] : nullptr;
+        double vd[NQ];   // new populations in FP64 (FP32 storage keeps their conserved moments)
         // planes that do not need row j + 2 DIR first, so its loads have time
 #pragma unroll
         for (int ps = 0; ps < 2; ++ps) {
 #pragma unroll
             for (int i = 0; i < NQ; ++i) {
                 if ((ps == 1) != (sgy(i) == -DIR)) continue;
-                const T v = plane_value<PH>(i, coll, a);
+                vd[i] = plane_value<PH>(i, coll, a);
+                const T v = (T)vd[i];
                 if (ROLE == ROLE_FIRST)
                     dst[i][lane] = KEEP_SELECT ? (keep ? W[C][i] : v) : v;
                 else
                     buf_store(v, rout, vout, base + (unsigned)i * pb);
+            }
+        }
+        if constexpr (keeps_cons<T>()) {
+            double cn[4];
+            cons_of(blocks_of(a), all_sums(vd), cn);
+            if (ROLE == ROLE_FIRST) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) ring->c[rs][k][lane] = keep ? CW[C][k] : cn[k];
+            } else {
+                const unsigned cb = (unsigned)((a.corg - 2 + (long)j * a.cpitch) * 8L);
+                const unsigned cpb = (unsigned)(a.cplane * 8L);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) buf_store(cn[k], rout, cons_off(vout), cb + (unsigned)k * cpb);
             }
         }
         // FP64: the kept values overwrite the new ones afterwards, on the few
@@ -445,7 +526,7 @@ struct Marcher {
                 for (int i = 0; i < NQ; ++i) dst[i][lane] = W[C][i];
             }
         }
-        velocity(W[E], U[E], V[E], a);
+        velocity(E, a);
     }
 
     // ROLE_FIRST: row j of step n + 1 on a high wall side (k = 0: the wall
@@ -457,9 +538,16 @@ struct Marcher {
         if (pass) {
             T v[NQ];
             load(v, j, a);
-            T(*dst)[MW] = ring->v[(j + 4) & (PRING - 1)];
+            const int sl = (j + 4) & (PRING - 1);
+            T(*dst)[MW] = ring->v[sl];
 #pragma unroll
             for (int i = 0; i < NQ; ++i) dst[i][lane] = v[i];
+            if constexpr (keeps_cons<T>()) {
+                double c[4];
+                load_cons(c, j, a);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) ring->c[sl][k][lane] = c[k];
+            }
         } else {
             ring_wall(a, ring, lane, 3, a.ny - 2, a.ny - 1, 1, k, k);
         }
@@ -494,12 +582,31 @@ struct Marcher {
         double f1[NQ], fw[NQ];
 #pragma unroll
         for (int i = 0; i < NQ; ++i) f1[i] = (double)buf_load(rout, vout, b1 + (unsigned)i * pb, (T*)nullptr);
+        if constexpr (keeps_cons<T>()) {
+            double c[4], ft[NQ];
+            const unsigned cb1 = (unsigned)((a.corg - 2 + (long)c1 * a.cpitch) * 8L), cpb = (unsigned)(a.cplane * 8L);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) c[k] = buf_load(rout, cons_off(vout), cb1 + (unsigned)k * cpb, (double*)nullptr);
+#pragma unroll
+            for (int i = 0; i < NQ; ++i) ft[i] = f1[i];
+            resync(blocks_of(a), ft, c, f1);
+        }
         wall_values(a, blocks_of(a), f1, side, fw);
 #pragma unroll
-        for (int i = 0; i < NQ; ++i) {
-            buf_store((T)fw[i], rout, vout, b0 + (unsigned)i * pb);
-            buf_store((T)(2.0 * fw[i] - f1[i]), rout, vout, b0 + step + (unsigned)i * pb);
-            buf_store((T)(3.0 * fw[i] - 2.0 * f1[i]), rout, vout, b0 + 2 * step + (unsigned)i * pb);
+        for (int r = 0; r < 3; ++r) {
+            double g[NQ];
+#pragma unroll
+            for (int i = 0; i < NQ; ++i) g[i] = (r == 0) ? fw[i] : wall_ghost(fw[i], f1[i], r);
+#pragma unroll
+            for (int i = 0; i < NQ; ++i) buf_store((T)g[i], rout, vout, b0 + (unsigned)r * step + (unsigned)i * pb);
+            if constexpr (keeps_cons<T>()) {
+                double c[4];
+                cons_of(blocks_of(a), all_sums(g), c);
+                const unsigned cb = (unsigned)((a.corg - 2 + (long)(cw + r * out) * a.cpitch) * 8L);
+                const unsigned cpb = (unsigned)(a.cplane * 8L);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) buf_store(c[k], rout, cons_off(vout), cb + (unsigned)k * cpb);
+            }
         }
     }
 
@@ -509,13 +616,13 @@ struct Marcher {
     {
         {
             CArgs& a = args();
-            load(W[3], j - 2 * DIR, a);
-            load(W[0], j - DIR, a);
-            load(W[1], j, a);
-            load(W[2], j + DIR, a);
-            velocity(W[0], U[0], V[0], a);
-            velocity(W[1], U[1], V[1], a);
-            velocity(W[2], U[2], V[2], a);
+            load_row(3, j - 2 * DIR, a);
+            load_row(0, j - DIR, a);
+            load_row(1, j, a);
+            load_row(2, j + DIR, a);
+            velocity(0, a);
+            velocity(1, a);
+            velocity(2, a);
         }
         start_carry();
     }
@@ -528,6 +635,14 @@ struct Marcher {
             W[0][i] = W[1][i];
             W[1][i] = W[2][i];
             W[2][i] = W[3][i];
+        }
+        if constexpr (keeps_cons<T>()) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                CW[0][k] = CW[1][k];
+                CW[1][k] = CW[2][k];
+                CW[2][k] = CW[3][k];
+            }
         }
         U[0] = U[1]; V[0] = V[1];
         U[1] = U[2]; V[1] = V[2];

@@ -77,6 +77,9 @@ _lib.mrtfd_macros.argtypes = [_H, _vp, _vp, _vp, _vp, ctypes.c_int]
 _lib.mrtfd_noneq.argtypes = [_H, ctypes.c_int, _vp, ctypes.c_int]
 _lib.mrtfd_get_f.argtypes = [_H, _vp, ctypes.c_int]
 _lib.mrtfd_set_f.argtypes = [_H, _vp, ctypes.c_int]
+_lib.mrtfd_state_planes.argtypes = [_H, ctypes.POINTER(ctypes.c_int)]
+_lib.mrtfd_get_state.argtypes = [_H, _vp, ctypes.c_int]
+_lib.mrtfd_set_state.argtypes = [_H, _vp, ctypes.c_int]
 _lib.mrtfd_sync.argtypes = [_H]
 _lib.mrtfd_steps_done.argtypes = [_H]
 _lib.mrtfd_steps_done.restype = ctypes.c_long
@@ -123,6 +126,35 @@ def device_memory():
     fr, tot = ctypes.c_size_t(0), ctypes.c_size_t(0)
     _check(_lib.mrtfd_device_memory(ctypes.byref(fr), ctypes.byref(tot)))
     return int(fr.value), int(tot.value)
+
+
+_lib.mrtfd_clock_stamp.argtypes = [_vp, _vp]
+
+
+def clock_stamp(out, index: int = 0, stream=None):
+    """Enqueue a stamp (per XCD: shader-clock cycles, 100 MHz ticks) into row
+    `index` of ``out``, an (n, 16) int64 CUDA tensor (zeroed beforehand), on
+    `stream` (default: torch's current stream)."""
+    if stream is None:
+        stream = _default_stream()
+    elif hasattr(stream, "cuda_stream"):
+        stream = stream.cuda_stream
+    if (not _is_device(out) or out.dim() != 2 or out.shape[1] != 16 or out.element_size() != 8
+            or not out.is_contiguous() or not 0 <= index < out.shape[0]):
+        raise ValueError("out must be a contiguous (n, 16) 64-bit CUDA tensor and index within it")
+    _check(_lib.mrtfd_clock_stamp(_vp(int(stream)), _vp(out.data_ptr() + 128 * int(index))))
+
+
+def clock_mhz(stamps, i0: int = 0, i1: int = 1) -> float:
+    """Average core clock (MHz) between two stamps (rows of the (n, 16) array
+    read back to the host): the mean over the XCDs that both stamps reached."""
+    vals = []
+    for x in range(8):
+        c0, r0 = stamps[i0][2 * x], stamps[i0][2 * x + 1]
+        c1, r1 = stamps[i1][2 * x], stamps[i1][2 * x + 1]
+        if r0 > 0 and r1 > r0 and c1 > c0:
+            vals.append((c1 - c0) / ((r1 - r0) / 100.0))
+    return sum(vals) / len(vals) if vals else float("nan")
 
 
 def constants(eta0: float = 2.5):
@@ -268,6 +300,27 @@ class Solver:
     def set_f(self, f):
         p, dev, keep = _ptr(f, (16, self.ny, self.nx))
         _check(_lib.mrtfd_set_f(self._h, _vp(p), dev))
+        return self
+
+    @property
+    def state_planes(self) -> int:
+        """Planes of the bitwise checkpoint: 16, or 20 in FP32 storage."""
+        k = ctypes.c_int()
+        _check(_lib.mrtfd_state_planes(self._h, ctypes.byref(k)))
+        return k.value
+
+    def get_state(self, out=None):
+        """The stored state, bit for bit, as (state_planes, ny, nx) doubles."""
+        shp = (self.state_planes, self.ny, self.nx)
+        if out is None:
+            out = np.zeros(shp)
+        p, dev, _ = _ptr(out, shp, writable=True)
+        _check(_lib.mrtfd_get_state(self._h, _vp(p), dev))
+        return out
+
+    def set_state(self, state):
+        p, dev, keep = _ptr(state, (self.state_planes, self.ny, self.nx))
+        _check(_lib.mrtfd_set_state(self._h, _vp(p), dev))
         return self
 
 

@@ -207,6 +207,16 @@ def fp32_vs_fp64_served(mrtfd, count=24):
               f"L1 max {max(x[5] for x in w):.2e}", flush=True)
 
 
+def fp32_vs_fp64_couette(mrtfd, n=20000):
+    for pr in (0.5, 1.0, 2.0):
+        out = {}
+        for prec in ("fp32", "fp64"):
+            c = W.couette(pr=pr)
+            c["params"]["precision"] = prec
+            out[prec], _ = solve(mrtfd, c, n)
+        record32(f"thermal Couette 4x200, Pr = {pr}", n, out["fp32"], out["fp64"], 1.4)
+
+
 def main():
     import torch
     assert torch.cuda.is_available(), "needs a GPU"
@@ -246,6 +256,7 @@ def main():
     fp32_vs_fp64_shock_interface(mrtfd)
     fp32_vs_fp64_batch(mrtfd)
     fp32_vs_fp64_served(mrtfd)
+    fp32_vs_fp64_couette(mrtfd)
     print("\nFP32 storage against FP64 storage (both on the GPU):\n")
     for r in FP32_ROWS:
         print(json.dumps(r))

@@ -194,16 +194,45 @@ def test_checkpoint_resume_is_bitwise(lib, precision):
     case = W.random_smooth(67, 13, seed=2, bcs=BC_SETS["walls_y"], jumps=True)
     p = dict(case["params"], precision=precision)
     with lib.Solver(p) as s:
+        assert s.state_planes == (20 if precision == "fp32" else 16)
         s.init(case["rho"], case["ux"], case["uy"], case["T"])
         s.step(10)
-        f10 = s.get_f()
+        st10 = s.get_state()
         s.step(10)
+        st20 = s.get_state()
         f20 = s.get_f()
-        s.set_f(f10)
-        assert np.array_equal(s.get_f(), f10)
+        s.set_state(st10)
+        assert np.array_equal(s.get_state(), st10)
         s.step(10)
+        assert np.array_equal(s.get_state(), st20)
         assert np.array_equal(s.get_f(), f20)
         assert s.steps_done == 10
+        if precision == "fp64":
+            # in FP64 storage the populations are the whole state
+            s.set_f(st10)
+            assert np.array_equal(s.get_f(), st10)
+            s.step(10)
+            assert np.array_equal(s.get_f(), f20)
+
+
+def test_fp32_populations_carry_their_stored_conserved_moments(lib, orc):
+    # get_f of FP32 storage gives populations whose conserved moments are the
+    # stored FP64 ones; set_f of them stores those moments again
+    case = W.random_smooth(67, 13, seed=4, bcs=BC_SETS["inflow_outflow"], jumps=True)
+    p = dict(case["params"], precision="fp32")
+    _, M, _, _ = orc.constants()
+    with lib.Solver(p) as s:
+        s.init(case["rho"], case["ux"], case["uy"], case["T"])
+        s.step(7)
+        st = s.get_state()
+        f = s.get_f()
+        c = np.einsum("ki,iyx->kyx", M[:4], f)
+        assert np.abs(c - st[16:]).max() <= 1e-14 * np.abs(st[16:]).max()
+        # the populations are the stored FP32 ones to within a few of their ulps
+        assert np.abs(f - st[:16]).max() <= 8 * np.spacing(np.abs(st[:16]).astype(np.float32)).max()
+        s.set_f(f)
+        st2 = s.get_state()
+        assert np.abs(st2[16:] - st[16:]).max() <= 1e-14 * np.abs(st[16:]).max()
 
 
 def test_nonfinite_is_reported(lib):
