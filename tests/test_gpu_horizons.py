@@ -1,0 +1,122 @@
+"""FP64 parity with the oracle over the configured run lengths.
+
+* Thermal Couette flow (Sec. IV-C) on the 4 x 200 channel for Pr = 0.5, 1, 2
+  from rest to steady state (some 10^5 steps), against the oracle's run to the
+  same step count (stored by tests/golden/make_oracle_horizons.py, which calls
+  only the oracle), at 1e-11; the GPU run also meets the steady-state
+  criterion at that step.
+* The 512-instance Riemann batch for its full 1000 steps in FP64 storage; a
+  spread of instances over every size against the oracle (one row: the
+  instances are uniform in y), at 1e-11 in rho, u_x and T; u_y exactly zero
+  (the flow's mirror symmetry).
+* The 4096 x 1024 shock-interface problem for 200 steps, in the launch
+  configuration the benchmark times, against the oracle on a window of 1504
+  columns cut by an outflow side, compared on a seeded sample of the nodes
+  more than 2n + 2 = 402 columns from the cut (stored by the same script).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from parity import TOL, rel_errors
+from paper_1305_4736_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1305_4736_amd import mrtfd
+    return mrtfd
+
+
+def worst(errs):
+    return max(max(v) for v in errs.values())
+
+
+def load(name):
+    with open(os.path.join(GOLDEN, name)) as fh:
+        return json.load(fh)
+
+
+@pytest.mark.parametrize("k", [0, 1, 2])
+def test_couette_steady_state_vs_oracle(lib, k):
+    g = load("couette_steady_oracle.json")["cases"][k]
+    c = W.couette(pr=g["pr"], gamma=g["gamma"])
+    n = g["steps"]
+    print(f"[horizon] couette Pr {g['pr']} to steady state: {n} steps", flush=True)
+    with lib.Solver(c["params"]) as s:
+        s.init(c["rho"], c["ux"], c["uy"], c["T"])
+        s.step(n - 1)
+        prev = s.macros()
+        s.step(1)
+        s.sync()
+        cur = s.macros()
+    res = max(np.abs(cur[q] - prev[q]).max() for q in (1, 2, 3))
+    assert res < 1e-10, res                       # steady by the same criterion
+    nx = c["params"]["nx"]
+    ref = tuple(np.repeat(np.asarray(g[q])[:, None], nx, 1) for q in ("rho", "ux", "uy", "T"))
+    errs = rel_errors(cur, ref, g["gamma"])
+    print(f"[horizon] couette Pr {g['pr']}: {errs}", flush=True)
+    assert worst(errs) <= TOL["fp64"], errs
+
+
+def test_riemann_batch_1000_steps_vs_oracle(lib, orc):
+    cases, _ = W.riemann_batch(n=512, precision="fp64")
+    print("[horizon] riemann batch 512 instances, 1000 steps, fp64", flush=True)
+    with lib.Batch(len(cases), precision="fp64") as b:
+        slots = [b.add(c["params"], c["rho"], c["ux"], c["uy"], c["T"], nsteps=1000) for c in cases]
+        b.step(1000)
+        b.status()
+        order = np.argsort([c["params"]["nx"] for c in cases])
+        pick = [int(k) for k in order[::51]] + [int(order[-1])]
+        got = {k: b.macros(slots[k]) for k in pick}
+    for k in pick:
+        c = cases[k]
+        p = dict(c["params"], ny=1)
+        row = lambda a: np.ascontiguousarray(a[:1])
+        fo = orc.run(p, row(c["rho"]), row(c["ux"]), row(c["uy"]), row(c["T"]), 1000)
+        mo = orc.macros(p, fo)
+        gamma = (p["b"] + 2.0) / p["b"]
+        mg = got[k]
+        # every row of the instance is the same run
+        assert all(np.array_equal(m, np.broadcast_to(m[:1], m.shape)) for m in mg)
+        # u_y of a flow uniform in y is zero by the mirror symmetry of the
+        # velocity set (Sec. II): the GPU path keeps it exactly; the oracle's
+        # dense sums and Gauss-Jordan inverse are not mirror-symmetric to the
+        # last bit and leave a rounding-level u_y that the scheme carries
+        # (up to 2e-11 of the flow speed after 1000 steps), so u_y is checked
+        # against the symmetry and the other fields against the oracle
+        assert np.all(mg[2] == 0.0)
+        errs = rel_errors(tuple(m[:1] for m in mg), mo, gamma)
+        uy = errs.pop("uy")
+        print(f"[horizon] riemann_{k} {p['nx']}x{c['params']['ny']}: {worst(errs):.2e} "
+              f"(oracle u_y {uy[1]:.1e} of the flow speed)", flush=True)
+        assert worst(errs) <= TOL["fp64"], (k, errs)
+        assert uy[1] <= 1e-9, (k, uy)
+
+
+def test_shock_interface_200_steps_vs_oracle_window(lib):
+    g = load("shock_interface_window_oracle.json")
+    case = W.shock_interface()
+    n = g["steps"]
+    print(f"[horizon] shock_interface 4096x1024 {n} steps vs the oracle window", flush=True)
+    with lib.Solver(case["params"]) as s:
+        assert s.steps_per_launch == 2            # the benchmark's launch configuration
+        s.init(case["rho"], case["ux"], case["uy"], case["T"])
+        s.step(n)
+        s.sync()
+        mg = s.macros()
+    ys, xs = np.asarray(g["y"]), np.asarray(g["x"])
+    gw = tuple(m[ys, xs] for m in mg)
+    ow = tuple(np.asarray(g[q]) for q in ("rho", "ux", "uy", "T"))
+    errs = rel_errors(gw, ow, 1.4)
+    print(f"[horizon] shock_interface window: {errs}", flush=True)
+    assert worst(errs) <= TOL["fp64"], errs
