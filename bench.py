@@ -45,6 +45,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -107,7 +108,12 @@ def algorithmic_bytes_per_node(precision: str) -> int:
     return 32 * (8 if precision == "fp64" else 4)
 
 
-def run_gpu(case, steps, warmup, noneq_every, log, per_launch=0):
+def run_gpu(case, steps, warmup, noneq_every, log, per_launch=0, keep_macros=False):
+    """The workload's timed steps.  The Delta* pass runs after every
+    `noneq_every` steps inside the timed region and is charged at that rate
+    into `value`: with fewer timed steps than that (the short default runs),
+    one pass is timed after the region and its time times steps / noneq_every
+    is added to the steps' wall time."""
     import torch
 
     from paper_1305_4736_amd import mrtfd
@@ -117,7 +123,8 @@ def run_gpu(case, steps, warmup, noneq_every, log, per_launch=0):
     dev = torch.device("cuda:0")
     fields = [torch.tensor(case[k], dtype=torch.float64, device=dev) for k in ("rho", "ux", "uy", "T")]
     delta = torch.empty((16, ny, nx), dtype=torch.float64, device=dev) if noneq_every else None
-    s = mrtfd.Solver(p, stream=torch.cuda.current_stream())
+    stream = torch.cuda.current_stream()
+    s = mrtfd.Solver(p, stream=stream)
     if per_launch:
         s.steps_per_launch = per_launch
     s.init(*fields)
@@ -127,63 +134,147 @@ def run_gpu(case, steps, warmup, noneq_every, log, per_launch=0):
     torch.cuda.synchronize()
     log(f"[bench] {case['name']} {p['precision']}: warm-up {warmup} steps done")
 
+    def noneq_timed():
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        s.noneq(star=True, out=delta)
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1)
+
+    stamps = torch.zeros((2, 16), dtype=torch.int64, device=dev)
     kernel_ms = 0.0
+    noneq_ms = []
     done = 0
+    mrtfd.clock_stamp(stamps, 0, stream)
     t0 = time.perf_counter()
     while done < steps:
         chunk = min(noneq_every or steps, steps - done)
         kernel_ms += s.step_timed(chunk)
         done += chunk
         if noneq_every and done % noneq_every == 0:
-            s.noneq(star=True, out=delta)
+            noneq_ms.append(noneq_timed())
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    mrtfd.clock_stamp(stamps, 1, stream)
     s.sync()
-    elapsed = t1 - t0
+    inside = len(noneq_ms)
+    if noneq_every and not noneq_ms:
+        noneq_ms.append(noneq_timed())
+    st = stamps.cpu().tolist()
+    clock = mrtfd.clock_mhz(st)
+    wall_steps = (t1 - t0) - 1e-3 * sum(noneq_ms[:inside])
+    noneq_avg = (sum(noneq_ms) / len(noneq_ms)) if noneq_ms else 0.0
+    charged = wall_steps + (steps / noneq_every if noneq_every else 0.0) * 1e-3 * noneq_avg
     nodes = nx * ny
     res = {
-        "elapsed_s": elapsed,
-        "ms_per_step": 1e3 * elapsed / steps,
-        "value": nodes * steps / elapsed,
+        "elapsed_s": charged,
+        "ms_per_step": 1e3 * charged / steps,
+        "value": nodes * steps / charged,
+        "steps_wall_s": wall_steps,
         "kernel_ms_avg": kernel_ms / steps,
+        "noneq_ms": noneq_avg,
+        "noneq_passes_in_region": inside,
+        "clock_mhz": clock,
         "nodes": nodes,
         "steps_per_launch": s.steps_per_launch,
     }
+    if keep_macros:
+        res["macros"] = s.macros()
     s.close()
     del delta
     torch.cuda.empty_cache()
-    log(f"[bench] {case['name']} {p['precision']}: {steps} steps in {elapsed:.3f} s, "
-        f"{res['value']:.4e} node-updates/s, kernel {res['kernel_ms_avg']:.4f} ms")
+    log(f"[bench] {case['name']} {p['precision']}: {steps} steps in {wall_steps:.4f} s (+ Delta* charged "
+        f"{charged - wall_steps:.5f} s), {res['value']:.4e} node-updates/s, kernel {res['kernel_ms_avg']:.4f} ms "
+        f"per step, core clock {clock:.0f} MHz")
     return res
 
 
+# VALU issue peak: 256 CUs x 4 SIMDs x 2.4 GHz, one wave64 instruction per
+# SIMD every 4 cycles (16 lanes per cycle: a wave64 FP64 FMA, or any other
+# wave64 VALU instruction, takes 4 cycles); 6.144e11 wave64 instructions/s,
+# which is the published 78.6 TFLOP/s FP64 vector peak when each lane does
+# an FMA.
+VALU_PEAK = 256 * 4 * 2.4e9 / 4
+
+
 def roofline(res, precision):
-    # the step timer brackets whole chunks of launches; with two steps per
-    # launch (even chunks) a launch lasts two step-times and processes two
-    # node-updates per node
+    """The step kernel's place under its two roofs, from its live average
+    launch time and the counters of the committed profile (when they were
+    taken on the current kernel code): VALU issue (SQ_INSTS_VALU per
+    dispatch) against the VALU peak, and HBM traffic (FETCH_SIZE +
+    WRITE_SIZE) against 8 TB/s.  `bound` is the roof the kernel is closer to;
+    `achieved`/`peak`/`frac` are that roof's.  The algorithmic HBM rate (256
+    or 128 bytes per node-update, two node-updates per node with two steps
+    per launch) is reported beside it as `hbm_effective`."""
     k = res["steps_per_launch"]
     bytes_launch = algorithmic_bytes_per_node(precision) * res["nodes"] * k
-    launch_ms = res["kernel_ms_avg"] * k
-    achieved = bytes_launch / (launch_ms * 1e-3) / 1e9
+    launch_s = res["kernel_ms_avg"] * k * 1e-3
     kernel = "k_march2" if k == 2 else "k_march"
-    traffic = None
+    eff = bytes_launch / launch_s / 1e9
+    ctr = None
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
-        if t.get("kernel_hash") == kernel_hash() and t.get("precision") == precision and t.get("kernel") == kernel:
-            traffic = t["hbm_bytes_per_launch"]
-    out = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-           "algorithmic_bytes_per_launch": bytes_launch, "kernel": kernel, "steps_per_launch": k,
-           "avg_launch_ms": round(launch_ms, 5)}
-    if k == 2:
-        out["note"] = ("two steps per launch: achieved counts 256 B per node-update, two per node; the launch "
-                       "moves about half that (traffic) and is bound by FP64 VALU issue")
+        if t.get("kernel_hash") == kernel_hash():
+            ctr = t.get("kernels", {}).get(f"{kernel}/{precision}")
+    traffic = ctr["hbm_bytes_per_launch"] if ctr else None
+    valu = ctr["valu_insts_per_launch"] if ctr else None
+    hbm = None if traffic is None else traffic / launch_s / 1e9
+    valu_rate = None if valu is None else valu / launch_s
+    clock = res.get("clock_mhz")
+    out = {"traffic": traffic, "kernel": kernel, "steps_per_launch": k, "avg_launch_ms": round(launch_s * 1e3, 5),
+           "hbm_effective": {"algorithmic_bytes_per_launch": bytes_launch, "GBs": round(eff, 2),
+                             "frac": round(eff / HBM_PEAK_GBS, 4)},
+           "hbm_measured": None if hbm is None else {"GBs": round(hbm, 2), "frac": round(hbm / HBM_PEAK_GBS, 4)},
+           "valu": None if valu is None else {
+               "insts_per_launch": valu, "per_s": valu_rate, "frac": round(valu_rate / VALU_PEAK, 4),
+               "frac_at_measured_clock": round(valu_rate / (VALU_PEAK * clock / 2400.0), 4) if clock else None},
+           "core_clock_mhz": round(clock, 1) if clock else None}
+    if valu is not None and hbm is not None and valu_rate / VALU_PEAK >= hbm / HBM_PEAK_GBS:
+        out.update({"bound": "alu", "achieved": valu_rate, "peak": VALU_PEAK, "unit": "VALU instr/s (wave64)",
+                    "frac": round(valu_rate / VALU_PEAK, 4)})
+    elif hbm is not None:
+        out.update({"bound": "hbm", "achieved": round(hbm, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(hbm / HBM_PEAK_GBS, 4)})
+    else:
+        # no counters for this code: the algorithmic rate is all there is
+        out.update({"bound": "hbm", "achieved": round(eff, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(eff / HBM_PEAK_GBS, 4), "note": "no counter profile of this kernel code: "
+                    "achieved is the algorithmic (effective) rate"})
     return out
 
 
+def macro_errors(a, b, gamma):
+    """Relative L1 / Linf errors of (rho, ux, uy, T) a against b: rho and T
+    over their own sums / maxima, velocities over the flow speed's (the
+    sound speed only for a flow slower than 1e-3 of it)."""
+    import numpy as np
+    speed = np.hypot(b[1], b[2])
+    cs = math.sqrt(gamma * float(np.abs(b[3]).max()))
+    slow = speed.max() < 1e-3 * cs
+    den_u = (cs * speed.size, cs) if slow else (float(speed.sum()), float(speed.max()))
+    out = {}
+    for k, name in enumerate(("rho", "ux", "uy", "T")):
+        d = np.abs(np.asarray(a[k]) - np.asarray(b[k]))
+        den = den_u if k in (1, 2) else (float(np.abs(b[k]).sum()), float(np.abs(b[k]).max()))
+        out[name] = [float(d.sum() / den[0]), float(d.max() / den[1])]
+    return out
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.lower().startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(log, nsteps=6):
-    """The FP64 oracle (serial C) on `nsteps` steps of the full grid."""
+    """The FP64 oracle (serial C, one thread) on `nsteps` steps of the full grid."""
     import oracle
     from paper_1305_4736_amd import workloads as W
 
@@ -197,7 +288,8 @@ def cpu_baseline(log, nsteps=6):
     log(f"[bench] cpu oracle: {nsteps} full-grid steps in {dt:.1f} s")
     return {"value": nodes * nsteps / dt, "unit": "node-updates/s", "cores": 1, "kind": "oracle",
             "sample": f"{nsteps} steps of the full {p['nx']}x{p['ny']} grid, serial FP64 C oracle "
-                      f"(gcc -O2), {dt:.1f} s"}
+                      f"(gcc -O2), {dt:.1f} s",
+            "host_nproc": os.cpu_count(), "cpu_model": cpu_model()}
 
 
 def run_limiters(log, steps=100):
@@ -276,18 +368,154 @@ def run_batched(steps, warmup, log, n=512):
             "shape_classes": shapes}
 
 
-def run_served(rate, seconds, log, drain, label, steps_per_tick=50, capacity=4096, cap_bytes=None):
-    """Poisson stream of MRT-FD solve requests served with continuous batching."""
+def run_served(rate, seconds, log, drain, label, steps_per_tick=50, capacity=4096, cap_bytes=None,
+               policy="fifo", latency_target_s=2.0, shed_after_s=4.0):
+    """Poisson stream of MRT-FD solve requests served with continuous
+    batching, admitted first come first served by memory (policy "fifo") or
+    with the resident work bounded by a latency target, smallest work first,
+    shedding what could not start within shed_after_s (policy "latency")."""
     from paper_1305_4736_amd import serve, workloads as W
 
     reqs = W.serve_stream(rate=rate, duration=seconds)
-    with serve.Server(capacity=capacity, steps_per_tick=steps_per_tick, max_resident_bytes=cap_bytes) as srv:
+    with serve.Server(capacity=capacity, steps_per_tick=steps_per_tick, max_resident_bytes=cap_bytes,
+                      policy=policy, latency_target_s=latency_target_s, shed_after_s=shed_after_s) as srv:
         rep = srv.run(reqs, duration=seconds, drain=drain, log=log)
     rep = {k: v for k, v in rep.items() if k != "results"}
     rep.update({"label": label, "rate_per_s": rate, "arrival_window_s": seconds, "drained": drain})
-    log(f"[bench] served ({label}): {rep['completed']}/{rep['requests']} done, p50 {rep['p50_s']:.3f} s, "
-        f"p99 {rep['p99_s']:.3f} s, achieved {rep['achieved_node_updates_per_s']:.3e} node-updates/s")
+    log(f"[bench] served ({label}): {rep['completed']}/{rep['requests']} done, {rep['shed']} shed, "
+        f"{rep['failed']} failed, p50 {rep['p50_s']:.3f} s, p99 {rep['p99_s']:.3f} s (completed only), "
+        f"achieved {rep['achieved_node_updates_per_s']:.3e} node-updates/s")
     return rep
+
+
+PROFILE_KERNELS = {"k_march2/fp64": "k_march2<0, double>", "k_march/fp64": "k_march<0, double>",
+                   "k_march2/fp32": "k_march2<0, float>", "k_march/fp32": "k_march<0, float>"}
+PROFILE_COMMAND = ("python3 bench.py --steps 20 --warmup 4 --no-cpu-baseline --no-limiters --no-batched "
+                   "--no-serve --pmc-copy-calibration")
+
+
+def _counter_rows(d):
+    """(kernel name, counter name, value) of every dispatch in a rocprofv3
+    --pmc CSV output directory."""
+    import csv
+    import glob
+    out = []
+    for path in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                out.append((r["Dispatch_Id"], r["Kernel_Name"], r["Counter_Name"], float(r["Counter_Value"])))
+    return out
+
+
+def summarize_profile(fetch_dir, write_dir, sq_dir, out_path):
+    """Per-launch HBM bytes and VALU instructions of the step kernels from
+    three rocprofv3 --pmc runs of PROFILE_COMMAND (FETCH_SIZE; WRITE_SIZE;
+    SQ_INSTS_VALU, SQ_WAVES, GRBM_GUI_ACTIVE), the byte counters scaled by
+    what they read for the plain 1 GiB device copy of the same run."""
+    def per_kernel(rows, counter):
+        acc = {}
+        for disp, name, cname, val in rows:
+            if cname != counter:
+                continue
+            acc.setdefault(name, {}).setdefault(disp, 0.0)
+            acc[name][disp] += val
+        return acc
+
+    fetch = per_kernel(_counter_rows(fetch_dir), "FETCH_SIZE")
+    write = per_kernel(_counter_rows(write_dir), "WRITE_SIZE")
+    sq_rows = _counter_rows(sq_dir)
+    valu = per_kernel(sq_rows, "SQ_INSTS_VALU")
+    waves = per_kernel(sq_rows, "SQ_WAVES")
+    gui = per_kernel(sq_rows, "GRBM_GUI_ACTIVE")
+    gib = float(1 << 30)
+    # the calibration copies: the dispatches that write 1 GiB, and the same
+    # dispatches (same program, same launch order) in the fetch pass
+    cal = {(name, disp) for name, d in write.items() for disp, v in d.items() if abs(v * 1024 - gib) < 0.01 * gib}
+    cw = [write[name][disp] for name, disp in cal]
+    cf = [fetch[name][disp] for name, disp in cal if disp in fetch.get(name, {})]
+    if not cw or len(cf) != len(cw):
+        raise RuntimeError("calibration copies not found in both passes")
+    fetch_factor = gib / (1024 * sum(cf) / len(cf))
+    write_factor = gib / (1024 * sum(cw) / len(cw))
+
+    def match(d, inst):
+        vals = [v for name, dd in d.items() if inst in name for v in dd.values()]
+        return (sum(vals) / len(vals), len(vals)) if vals else (None, 0)
+
+    nodes = 4096 * 1024
+    kernels = {}
+    for key, inst in PROFILE_KERNELS.items():
+        kname, prec = key.split("/")
+        f, nf = match(fetch, inst)
+        w, nw = match(write, inst)
+        v, nv = match(valu, inst)
+        wv, _ = match(waves, inst)
+        g, _ = match(gui, inst)
+        if f is None or w is None:
+            continue
+        fb, wb = 1024 * f * fetch_factor, 1024 * w * write_factor
+        k = 2 if kname == "k_march2" else 1
+        alg = algorithmic_bytes_per_node(prec) * nodes * k
+        kernels[key] = {"instance": inst, "dispatches": {"fetch": nf, "write": nw, "sq": nv},
+                        "fetch_bytes_per_launch": round(fb), "write_bytes_per_launch": round(wb),
+                        "hbm_bytes_per_launch": round(fb + wb), "algorithmic_bytes_per_launch": alg,
+                        "hbm_over_algorithmic": round((fb + wb) / alg, 4),
+                        "valu_insts_per_launch": v, "waves_per_launch": wv, "valu_insts_per_wave": v / wv if wv else None,
+                        "grbm_gui_active_per_launch": g}
+    out = {"workload": "shock_interface_4096x1024", "kernel_hash": kernel_hash(),
+           "command": PROFILE_COMMAND, "passes": ["FETCH_SIZE", "WRITE_SIZE", "SQ_INSTS_VALU SQ_WAVES GRBM_GUI_ACTIVE"],
+           "copy_calibration": {"bytes": int(gib), "fetch_factor": fetch_factor, "write_factor": write_factor},
+           "kernels": kernels}
+    with open(out_path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    return out
+
+
+def summarize_trace(trace_dir, out_path, command, timed=(2, 12), kernel="k_march2<0, double>"):
+    """Markdown summary of a rocprofv3 --kernel-trace --stats CSV run of the
+    benchmark: the per-kernel statistics, and the durations of the headline
+    kernel's dispatches in order, with their mean over the dispatches of the
+    timed region (`timed`: first and one-past-last dispatch index; the default
+    run's FP64 workload launches two pairs and a single step in its 5-step
+    warm-up, then 10 pairs in its 20 timed steps)."""
+    import csv
+    import glob
+    stats = []
+    for path in glob.glob(os.path.join(trace_dir, "**", "*kernel_stats.csv"), recursive=True):
+        with open(path) as fh:
+            stats += list(csv.DictReader(fh))
+    durs = []
+    for path in glob.glob(os.path.join(trace_dir, "**", "*kernel_trace.csv"), recursive=True):
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                if kernel in r["Kernel_Name"]:
+                    durs.append((int(r["Start_Timestamp"]), (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3))
+    durs.sort()
+    us = [d for _, d in durs]
+    a, b = timed
+    lines = [f"# `{kernel}` on the 4096x1024 shock-interface workload: kernel trace of the benchmark", "",
+             f"Command (repo root, on the GPU machine): `{command}`", "",
+             f"Dispatches of `{kernel}`: {len(us)}; mean over all {sum(us) / max(len(us), 1):.2f} us.",
+             f"Timed region of the FP64 run (dispatches {a + 1}..{b}): mean {sum(us[a:b]) / max(b - a, 1):.2f} us "
+             f"over {len(us[a:b])} dispatches.", "",
+             "Durations in order (us), first 120 dispatches:", "",
+             " ".join(f"{x:.1f}" for x in us[:120]), "",
+             "| kernel | calls | total us | average us | % |", "|---|---|---|---|---|"]
+    def num(r, *keys):
+        for k in keys:
+            if k in r and r[k] not in ("", None):
+                return float(r[k])
+        return float("nan")
+    for r in sorted(stats, key=lambda r: -num(r, "TotalDurationNs"))[:25]:
+        name = r.get("Name", "?")
+        name = name[5:] if name.startswith("void ") else name
+        name = name.replace("(anonymous namespace)::", "").split("(")[0]
+        lines.append(f"| `{name}` | {int(num(r, 'Calls'))} | "
+                     f"{num(r, 'TotalDurationNs') / 1e3:.1f} | {num(r, 'AverageNs') / 1e3:.2f} | "
+                     f"{num(r, 'Percentage'):.2f} |")
+    with open(out_path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    return sum(us[a:b]) / max(b - a, 1)
 
 
 def copy_calibration(log, nbytes=1 << 30):
@@ -316,13 +544,28 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-limiters", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-seconds", type=float, default=8.0)
+    # the served stream's arrival window: 60 s as configured
+    ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     # the highest of 20, 25, 30 and 35 requests/s whose queue stayed bounded
     # (at 30 the offered load exceeds what the device achieves)
     ap.add_argument("--sustainable-rate", type=float, default=25.0)
     ap.add_argument("--light-rate", type=float, default=15.0)
+    ap.add_argument("--summarize-profile", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "SQ_DIR"),
+                    help="write the counter summary of three rocprofv3 --pmc runs of the profile command "
+                         "to profiles/ and exit (no GPU)")
+    ap.add_argument("--summarize-trace", nargs=2, metavar=("TRACE_DIR", "OUT_MD"),
+                    help="write the markdown summary of a rocprofv3 kernel trace of this benchmark and exit")
+    ap.add_argument("--trace-command", default="rocprofv3 --kernel-trace --stats --output-format csv -d TRACE_DIR "
+                    "-o trace -- python3 bench.py --gpus 1 --steps 20 --warmup 5")
     args = ap.parse_args()
+    if args.summarize_trace:
+        print(summarize_trace(args.summarize_trace[0], args.summarize_trace[1], args.trace_command))
+        return
+    if args.summarize_profile:
+        out = summarize_profile(*args.summarize_profile, TRAFFIC_FILE)
+        print(json.dumps(out, indent=1))
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -343,7 +586,8 @@ def main():
         copy_calibration(log)
 
     case = W.shock_interface(precision="fp64")
-    res = run_gpu(case, args.steps, args.warmup, args.noneq_every, log, args.steps_per_launch)
+    res = run_gpu(case, args.steps, args.warmup, args.noneq_every, log, args.steps_per_launch,
+                  keep_macros=not args.no_fp32)
     rl = roofline(res, "fp64")
 
     extra = {}
@@ -353,15 +597,22 @@ def main():
         rl1 = roofline(r1, "fp64")
         extra["fp64_one_step_per_launch"] = {"value": r1["value"], "ms_per_step": r1["ms_per_step"],
                                              "kernel_ms_per_step": round(r1["kernel_ms_avg"], 5),
-                                             "roofline_frac": rl1["frac"], "achieved_GBs": rl1["achieved"]}
+                                             "core_clock_mhz": round(r1["clock_mhz"], 1), "roofline": rl1}
     if not args.no_fp32:
         case32 = W.shock_interface(precision="fp32")
-        r32 = run_gpu(case32, args.steps, args.warmup, args.noneq_every, log, args.steps_per_launch)
+        r32 = run_gpu(case32, args.steps, args.warmup, args.noneq_every, log, args.steps_per_launch,
+                      keep_macros=True)
         rl32 = roofline(r32, "fp32")
+        # the same steps in both storage precisions: FP32 against FP64
+        err = macro_errors(r32.pop("macros"), res.pop("macros"), 1.4)
         extra["fp32_storage"] = {"value": r32["value"], "ms_per_step": r32["ms_per_step"],
                                  "steps_per_launch": r32["steps_per_launch"],
-                                 "roofline_frac": rl32["frac"], "achieved_GBs": rl32["achieved"],
-                                 "speedup_vs_fp64": r32["value"] / res["value"]}
+                                 "core_clock_mhz": round(r32["clock_mhz"], 1), "roofline": rl32,
+                                 "speedup_vs_fp64": r32["value"] / res["value"],
+                                 "rel_error_vs_fp64_after_timed_steps": {
+                                     "steps": args.warmup + args.steps, "L1_Linf": err,
+                                     "max": max(max(v) for v in err.values()),
+                                     "velocity_denominator": "flow speed"}}
         if not args.steps_per_launch and r32["steps_per_launch"] == 2:
             r1 = run_gpu(case32, args.steps, args.warmup, args.noneq_every, log, 1)
             extra["fp32_one_step_per_launch"] = {"value": r1["value"], "ms_per_step": r1["ms_per_step"],
@@ -376,7 +627,12 @@ def main():
         extra["batched"] = run_batched(max(args.steps // 2, 20), 5, log)
     if not args.no_serve:
         extra["served"] = run_served(args.serve_rate, args.serve_seconds, log, drain=False,
-                                     label="offered load as specified (overloaded), stopped at the end of arrivals")
+                                     label="offered load as specified (overloaded), first come first served by "
+                                           "memory, stopped at the end of arrivals")
+        extra["served_latency_policy"] = run_served(
+            args.serve_rate, args.serve_seconds, log, drain=False, policy="latency",
+            label="offered load as specified (overloaded), resident work bounded by a 2 s latency target, "
+                  "smallest work first, shed beyond 4 s of expected wait; stopped at the end of arrivals")
         extra["served_sustainable"] = run_served(args.sustainable_rate, args.serve_seconds, log, drain=True,
                                                  label="highest sustainable rate measured, drained")
         extra["served_light"] = run_served(args.light_rate, args.serve_seconds, log, drain=True,
@@ -392,6 +648,9 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": res["ms_per_step"],
+        "steps_wall_ms_per_step": round(1e3 * res["steps_wall_s"] / args.steps, 5),
+        "noneq_star_ms": round(res["noneq_ms"], 4),
+        "noneq_star_passes_in_timed_region": res["noneq_passes_in_region"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

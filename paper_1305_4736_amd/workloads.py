@@ -207,16 +207,19 @@ def paper_heavy_light(precision="fp64"):
 # the GPU alike).
 SCREEN_RATIO = 5.0
 SCREEN_MACH = 1.0
+# (temperature ratio, pressure ratio, Mach number) bounds of a screen
+SCREEN = (SCREEN_RATIO, SCREEN_RATIO, SCREEN_MACH)
 
 
-def riemann_batch(n=512, seed=13054736, nsteps=1000, precision="fp32"):
+def riemann_batch(n=512, seed=13054736, nsteps=1000, precision="fp32", screen=SCREEN):
     """Independent two-state Riemann problems with log-uniform Nx in
     [128, 4096], Ny in [1, 256]; rho, p ~ U[0.1, 10], u ~ U[-0.5, 0.5],
-    gamma ~ U[1.1, 1.67]; states (and gamma) are redrawn while the pressure or
-    the temperature ratio exceeds SCREEN_RATIO or a side is supersonic, then
-    rescaled to T_max = 1
+    gamma ~ U[1.1, 1.67]; states (and gamma) are redrawn while the
+    temperature ratio, the pressure ratio or a side's Mach number exceeds the
+    screen's bounds, then rescaled to T_max = 1
     (p /= T_ref, u /= sqrt(T_ref)).  dt = 0.01 dx, dt*s = 0.5 (s_5..7) and 1
-    (the others)."""
+    (the others).  Returns (cases, redraws)."""
+    t_max, p_max, m_max = screen
     rng = np.random.default_rng(seed)
     cases = []
     redraws = 0
@@ -230,8 +233,7 @@ def riemann_batch(n=512, seed=13054736, nsteps=1000, precision="fp32"):
             gamma = rng.uniform(1.1, 1.67)
             Tl, Tr = pl / rl, pr / rr
             mach = max(abs(ul) / math.sqrt(gamma * Tl), abs(ur) / math.sqrt(gamma * Tr))
-            if (max(Tl, Tr) / min(Tl, Tr) <= SCREEN_RATIO and max(pl, pr) / min(pl, pr) <= SCREEN_RATIO
-                    and mach <= SCREEN_MACH):
+            if max(Tl, Tr) / min(Tl, Tr) <= t_max and max(pl, pr) / min(pl, pr) <= p_max and mach <= m_max:
                 break
             redraws += 1
         Tref = max(Tl, Tr)

@@ -1,6 +1,8 @@
 """Host-side checks of bench.py's bookkeeping (no GPU needed): the hash that
-keys the stored traffic counters to the kernel code ignores comments and
-whitespace but not code, and it matches the stored counters' hash."""
+keys the stored counter profile to the kernel code ignores comments and
+whitespace but not code, and it matches the stored profile's hash; the
+roofline takes the nearer of the VALU-issue and HBM roofs; FP32 errors are
+measured against the flow speed."""
 import json
 import os
 import sys
@@ -23,8 +25,49 @@ def test_code_tokens_ignore_comments_and_spacing():
     assert bench.code_tokens(p, "#") != bench.code_tokens(p.replace("-O3", "-O2"), "#")
 
 
-def test_stored_traffic_matches_the_kernel_code():
+def test_stored_counters_match_the_kernel_code():
     t = json.load(open(bench.TRAFFIC_FILE))
     assert t["kernel_hash"] == bench.kernel_hash()
-    assert t["algorithmic_bytes_per_launch"] == 2 * 256 * 4096 * 1024
-    assert 0 < t["hbm_bytes_per_launch"] < t["algorithmic_bytes_per_launch"]
+    k = t["kernels"]["k_march2/fp64"]
+    assert k["algorithmic_bytes_per_launch"] == 2 * 256 * 4096 * 1024
+    assert 0 < k["hbm_bytes_per_launch"] < k["algorithmic_bytes_per_launch"]
+    assert k["valu_insts_per_launch"] > 0
+    for key in ("k_march/fp64", "k_march2/fp32", "k_march/fp32"):
+        assert t["kernels"][key]["hbm_bytes_per_launch"] > 0
+
+
+def test_roofline_takes_the_nearer_roof(monkeypatch, tmp_path):
+    # a launch of 0.25 ms moving 1.0e9 bytes (4 TB/s, half the HBM peak) and
+    # issuing 1.2e8 VALU instructions (0.78 of the VALU issue peak): VALU-bound
+    ctr = {"kernel_hash": bench.kernel_hash(), "kernels": {"k_march2/fp64": {
+        "hbm_bytes_per_launch": 1.0e9, "valu_insts_per_launch": 1.2e8}}}
+    f = tmp_path / "c.json"
+    f.write_text(json.dumps(ctr))
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
+    res = {"steps_per_launch": 2, "nodes": 4096 * 1024, "kernel_ms_avg": 0.125, "clock_mhz": 2000.0}
+    r = bench.roofline(res, "fp64")
+    assert r["bound"] == "alu" and abs(r["frac"] - 1.2e8 / 0.25e-3 / bench.VALU_PEAK) < 1e-3
+    assert abs(r["hbm_measured"]["frac"] - 0.5) < 1e-3
+    assert abs(r["hbm_effective"]["GBs"] - 2 * 256 * 4096 * 1024 / 0.25e-3 / 1e9) < 0.1
+    assert abs(r["valu"]["frac_at_measured_clock"] - r["frac"] * 2400 / 2000) < 1e-3
+    # with few VALU instructions the HBM roof is the nearer one
+    ctr["kernels"]["k_march2/fp64"]["valu_insts_per_launch"] = 1.0e7
+    f.write_text(json.dumps(ctr))
+    assert bench.roofline(res, "fp64")["bound"] == "hbm"
+    # counters of other code are not used
+    ctr["kernel_hash"] = "0" * 16
+    f.write_text(json.dumps(ctr))
+    r = bench.roofline(res, "fp64")
+    assert r["traffic"] is None and r["valu"] is None and "note" in r
+
+
+def test_macro_errors_use_the_flow_speed():
+    import numpy as np
+    ref = (np.ones((2, 3)), np.full((2, 3), 0.1), np.zeros((2, 3)), np.ones((2, 3)))
+    got = (ref[0], ref[1] + 1e-6, ref[2], ref[3])
+    e = bench.macro_errors(got, ref, 1.4)
+    assert abs(e["ux"][1] - 1e-5) < 1e-12 and e["uy"][1] == 0.0
+    # a fluid at rest falls back to the sound speed
+    still = (ref[0], np.zeros((2, 3)), ref[2], ref[3])
+    e = bench.macro_errors((ref[0], still[1] + 1e-6, ref[2], ref[3]), still, 1.4)
+    assert abs(e["ux"][1] - 1e-6 / 1.4 ** 0.5) < 1e-12

@@ -2,8 +2,12 @@
 with a stand-in for the library's batches: first come, first served within a
 precision, the memory budget never exceeded and never overtaken, a full batch
 letting the other precision pass, every request stepped exactly its budget,
-every request answered once, and a device allocation that fails although the
-budget allows it (the request waits; the budget shrinks to what fit)."""
+every request answered once, a device allocation that fails although the
+budget allows it (the request waits; the budget shrinks to what fit), a slot
+the device flags non-finite (failed, not completed, out of the latencies),
+and the latency policy (resident work bounded, smallest work first,
+shedding)."""
+import numpy as np
 import pytest
 
 from paper_1305_4736_amd import mrtfd, serve
@@ -17,21 +21,28 @@ class FakeBatch:
         self.capacity, self.precision = capacity, precision
         self.slots = {}
         self.ledger = ledger
+        self.flags = np.zeros(capacity, dtype=np.int32)
+        self.poison = ledger.get("poison", set())     # request keys whose solve goes non-finite
 
     def add(self, p, rho, ux, uy, T, nsteps):
         assert rho.shape == (p["ny"], p["nx"])
         k = min(set(range(self.capacity)) - set(self.slots))
-        self.slots[k] = {"left": nsteps, "done": 0, "fp": mrtfd.footprint(p), "nsteps": nsteps}
+        self.slots[k] = {"left": nsteps, "done": 0, "fp": mrtfd.footprint(p), "nsteps": nsteps,
+                         "key": (self.precision, p["nx"], p["ny"], nsteps)}
+        self.flags[k] = 0
         self.ledger["resident"] += self.slots[k]["fp"]
         self.ledger["peak"] = max(self.ledger["peak"], self.ledger["resident"])
         self.ledger["admitted"].append((self.precision, p["nx"], p["ny"], nsteps))
         return k
 
     def step(self, n):
-        for s in self.slots.values():
+        self.ledger.setdefault("ticks", []).append(sum(s["left"] > 0 for s in self.slots.values()))
+        for k, s in self.slots.items():
             d = min(n, s["left"])
             s["left"] -= d
             s["done"] += d
+            if d and s["key"] in self.poison:
+                self.flags[k] = 1
 
     def remaining(self, k):
         return self.slots[k]["left"]
@@ -40,11 +51,11 @@ class FakeBatch:
         return self.slots[k]["done"]
 
     def macros(self, k):
-        return ("macros", self.precision, k)
+        return tuple(np.full((1, 2), float(k)) for _ in range(4))
 
     def remove(self, k):
         s = self.slots.pop(k)
-        assert s["done"] == s["nsteps"]
+        assert s["done"] == s["nsteps"] or s["key"] in self.poison
         self.ledger["resident"] -= s["fp"]
         self.ledger["finished"] += 1
 
@@ -52,7 +63,12 @@ class FakeBatch:
         pass
 
     def status(self):
-        pass
+        if self.flags.any():
+            err = mrtfd.NonFiniteError(mrtfd.ENONFINITE, "flagged")
+            err.flags = self.flags.copy()
+            self.flags[:] = 0
+            raise err
+        return self.flags.copy()
 
     def close(self):
         pass
@@ -193,3 +209,58 @@ def test_requests_that_cannot_fit_alone_are_rejected():
     srv = make_server(64, device, led)
     rep = srv.run(reqs, realtime=False)
     assert rep["rejected"] == 1 and rep["completed"] == len(reqs) - 1
+
+
+def test_flagged_request_fails_and_is_left_out():
+    reqs = small_stream(16, seed=7)
+    bad = {key(reqs[3][1]), key(reqs[9][1])}
+    led = dict(ledger(), poison=bad)
+    with make_server(capacity=64, budget=1 << 40, ledger=led, steps_per_tick=100) as srv:
+        rep = srv.run(reqs, realtime=False, drain=True)
+    assert rep["failed"] == 2 and rep["failed_requests"] == [3, 9]
+    assert rep["completed"] == len(reqs) - 2 and 3 not in rep["results"] and 9 not in rep["results"]
+    # their slots were freed at once (they did not run their whole budget)
+    assert led["resident"] == 0 and led["finished"] == len(reqs)
+
+
+def test_non_finite_result_fails():
+    # a result the flag did not catch (the last step's output) is checked on the host
+    reqs = small_stream(6, seed=8)
+
+    class NaNBatch(FakeBatch):
+        def macros(self, k):
+            out = super().macros(k)
+            if self.slots[k]["key"] == key(reqs[2][1]):
+                out[0][0, 0] = np.nan
+            return out
+
+    led = ledger()
+    srv = serve.Server(capacity=64, steps_per_tick=300, reserve_bytes=0, keep_results=True,
+                       batch_factory=lambda cap, prec, lim: NaNBatch(cap, prec, lim, led), memory=(1 << 40, 1 << 40))
+    rep = srv.run(reqs, realtime=False)
+    assert rep["failed_requests"] == [2] and rep["completed"] == 5
+
+
+def test_latency_policy_bounds_resident_work_and_sheds():
+    reqs = small_stream(60, seed=9)
+    w = lambda s: s["params"]["nx"] * s["params"]["ny"] * s["nsteps"]
+    works = sorted(w(s) for _, s in reqs)
+    # a rate at which a tick of 100 steps is "1 s": the target holds about
+    # the median request, the shedding bound a few of them
+    rate = float(np.median(works))
+    led = ledger()
+    srv = serve.Server(capacity=64, steps_per_tick=100, reserve_bytes=0, keep_results=True,
+                       batch_factory=lambda cap, prec, lim: FakeBatch(cap, prec, lim, led),
+                       memory=(1 << 40, 1 << 40), policy="latency", latency_target_s=1.0,
+                       shed_after_s=6.0, rate_guess=rate, measure_rate=False)
+    rep = srv.run(reqs, realtime=False)
+    # every request is answered once: completed, or shed
+    assert rep["completed"] + rep["shed"] == len(reqs) and rep["failed"] == 0
+    assert rep["shed"] > 0 and set(rep["shed_requests"]).isdisjoint(rep["results"])
+    # the shed ones are the largest (smallest work first)
+    done_w = [w(reqs[i][1]) for i in rep["results"]]
+    shed_w = [w(reqs[i][1]) for i in rep["shed_requests"]]
+    assert np.median(shed_w) > np.median(done_w)
+    # admitted in order of work within the first admission round
+    first = [a for a in led["admitted"]][:3]
+    assert [a[1] * a[2] * a[3] for a in first] == sorted(a[1] * a[2] * a[3] for a in first)
