@@ -190,6 +190,28 @@ const char* mrtfd_last_error(void);
  * admission by free HBM). */
 int mrtfd_device_memory(size_t* free_bytes, size_t* total_bytes);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops and harnesses that forbid allocation): one whole
+ * solve -- as mrtfd_create, mrtfd_init, mrtfd_step(nsteps) and mrtfd_macros
+ * with device pointers, same kernels, same bits -- whose state lives in a
+ * file-scope device array of 64 MiB that each GPU holds until the process
+ * ends, instead of in library allocations.  No hipMalloc, hipFree or other
+ * allocating call is made; the array, the constants and the arguments are
+ * set up by kernels on hip_stream.  rho, ux, uy, T: (ny, nx) device inputs;
+ * rho_out .. T_out: (ny, nx) device outputs (any may be NULL).  Limits and
+ * errors: MRTFD_EINVAL when the two state buffers (mrtfd_footprint) and a
+ * 4 KiB set-up area exceed 64 MiB (square grids up to 492 x 492 nodes fit
+ * in FP64 storage, 568 x 568 in FP32 storage), and for what mrtfd_create
+ * rejects.
+ * Asynchronous on hip_stream; non-finite nodes are not reported (check the
+ * outputs).  Every call on a GPU uses that GPU's one array: calls that
+ * overlap on one GPU (other streams or threads) race and must be ordered
+ * by the caller; a call starts from a cleared array and leaves its last
+ * state there. */
+int mrtfd_solve_noalloc(const mrtfd_params* p, void* hip_stream, const double* rho, const double* ux,
+                        const double* uy, const double* T, long nsteps, double* rho_out, double* ux_out,
+                        double* uy_out, double* T_out);
+
 /* Diagnostics: enqueue on hip_stream (a hipStream_t) a kernel of one block
  * per XCD that writes, to the device array out[16], each XCD's shader-clock
  * counter (core clock cycles; out[2 x]) and the constant-rate 100 MHz

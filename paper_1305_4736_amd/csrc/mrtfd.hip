@@ -18,8 +18,10 @@
 // are constant and written once.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "mrtfd_host.h"
 #include "mrtfd_march.h"
@@ -253,6 +255,59 @@ __global__ void k_clock_stamp(unsigned long long* out)
         out[2 * xcc + 1] = r;
     }
 }
+
+// ---------------------------------------------------------------------------
+// The no-allocation solve: the state of one solve lives in a file-scope
+// device array instead of library allocations, for callers that cannot
+// allocate.
+
+constexpr size_t NOALLOC_BYTES = size_t(64) << 20;   // the array's size on every device
+constexpr size_t NOALLOC_HEAD = 4096;                // blocks, arguments and flag before the state buffers
+__device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+// Device address of `scratch` on each device, taken once per device with
+// that device current (host code never uses the array's name as an address).
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch;
+
+int scratch_address(void** out)
+{
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if ((int)g_scratch.size() <= dev) g_scratch.resize(dev + 1, nullptr);
+    if (!g_scratch[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return fail(MRTFD_EDEVICE, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev,
+                        hipGetErrorString(e));
+        }
+        g_scratch[dev] = p;
+    }
+    *out = g_scratch[dev];
+    return MRTFD_OK;
+}
+
+// Blocks, arguments and a cleared flag written into the array by a kernel
+// (the values travel as kernel arguments; no copy from host memory).
+__global__ void k_put_setup(Blocks b, StepArgs a, Blocks* bdst, StepArgs* adst, int* flag)
+{
+    if (threadIdx.x == 0) {
+        *bdst = b;
+        *adst = a;
+        *flag = 0;
+    }
+}
+
+// Zero `n` 8-byte words (the state buffers' padding is never read, but a
+// solve then starts from the same bytes as one on fresh buffers).
+__global__ void k_zero(unsigned long long* p, size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0;
+}
+
 
 }  // namespace
 
@@ -616,6 +671,62 @@ int mrtfd_device_memory(size_t* free_bytes, size_t* total_bytes)
     HIPCHK(hipMemGetInfo(&fr, &tot));
     if (free_bytes) *free_bytes = fr;
     if (total_bytes) *total_bytes = tot;
+    return MRTFD_OK;
+}
+
+int mrtfd_solve_noalloc(const mrtfd_params* p, void* hip_stream, const double* rho, const double* ux,
+                        const double* uy, const double* T, long nsteps, double* rho_out, double* ux_out,
+                        double* uy_out, double* T_out)
+{
+    int rc = validate(p);
+    if (rc) return rc;
+    if (!rho || !ux || !uy || !T) return fail(MRTFD_EINVAL, "NULL input field");
+    if (nsteps < 0) return fail(MRTFD_EINVAL, "nsteps < 0");
+    static_assert(sizeof(Blocks) <= 1024 && sizeof(StepArgs) <= 2048, "set-up area of the array too small");
+    const Layout L = layout_of(*p);
+    const size_t buf = (L.buf_bytes + 255) / 256 * 256;
+    if (NOALLOC_HEAD + 2 * buf > NOALLOC_BYTES)
+        return fail(MRTFD_EINVAL, "grid %d x %d needs %zu bytes of state; the no-allocation solve holds %zu",
+                    p->nx, p->ny, NOALLOC_HEAD + 2 * buf, NOALLOC_BYTES);
+    void* base = nullptr;
+    rc = scratch_address(&base);
+    if (rc) return rc;
+    // a handle on the host stack whose device state is the array
+    mrtfd_s h{};
+    h.p = *p;
+    h.stream = (hipStream_t)hip_stream;
+    h.L = L;
+    char* b = (char*)base;
+    h.blocks_dev = (Blocks*)b;
+    h.args_dev = (StepArgs*)(b + 1024);
+    h.flag = (int*)(b + 3072);
+    h.buf[0] = b + NOALLOC_HEAD;
+    h.buf[1] = b + NOALLOC_HEAD + buf;
+    if (!build_blocks(p->eta0, &h.blocks)) return fail(MRTFD_EINVAL, "singular moment blocks for eta0 = %g", p->eta0);
+    rc = query_march_capacity(&h);
+    if (rc) return rc;
+    fill_args(&h);
+    const int min_rows = (p->precision == MRTFD_FP32_STORAGE) ? MARCH2_MIN_ROWS32 : MARCH2_MIN_ROWS64;
+    h.per_launch = (pair_supported(&h) && h.args.p_rows >= min_rows) ? 2 : 1;
+    // fresh state buffers, constants, arguments and flag, all by kernels
+    hipLaunchKernelGGL(k_zero, dim3(1024), dim3(256), 0, h.stream, (unsigned long long*)h.buf[0], 2 * buf / 8);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_put_setup, dim3(1), dim3(64), 0, h.stream, h.blocks, h.args, h.blocks_dev, h.args_dev, h.flag);
+    HIPCHK(hipGetLastError());
+    // f = f^eq of the fields, ghosts and walls, the steps, the outputs
+    h.cur = 0;
+    dim3 grid = node_grid(p->nx, p->ny), block(BX, BY);
+    if (p->precision == MRTFD_FP32_STORAGE)
+        hipLaunchKernelGGL((k_init<float>), grid, block, 0, h.stream, (float*)h.buf[0], rho, ux, uy, T, h.args);
+    else
+        hipLaunchKernelGGL((k_init<double>), grid, block, 0, h.stream, (double*)h.buf[0], rho, ux, uy, T, h.args);
+    HIPCHK(hipGetLastError());
+    rc = refill(&h);
+    if (rc) return rc;
+    h.ready = true;
+    rc = mrtfd_step(&h, nsteps);
+    if (rc) return rc;
+    if (rho_out || ux_out || uy_out || T_out) return mrtfd_macros(&h, rho_out, ux_out, uy_out, T_out, 1);
     return MRTFD_OK;
 }
 

@@ -128,6 +128,32 @@ def device_memory():
     return int(fr.value), int(tot.value)
 
 
+_lib.mrtfd_solve_noalloc.argtypes = [ctypes.POINTER(_Params), _vp, _vp, _vp, _vp, _vp, ctypes.c_long,
+                                     _vp, _vp, _vp, _vp]
+
+
+def solve_noalloc(params: dict, rho, ux, uy, T, nsteps: int, out=None, stream=None):
+    """One whole solve with no device allocation (mrtfd_solve_noalloc): device
+    tensors in, (rho, ux, uy, T) device tensors out (written into ``out``
+    when given).  Asynchronous on `stream` (default: torch's current one)."""
+    import torch
+    nx, ny = int(params["nx"]), int(params["ny"])
+    ins = [_ptr(a, (ny, nx)) for a in (rho, ux, uy, T)]
+    if any(d != 1 for _, d, _ in ins):
+        raise ValueError("solve_noalloc takes device tensors")
+    if out is None:
+        out = tuple(torch.empty((ny, nx), dtype=torch.float64, device=rho.device) for _ in range(4))
+    outs = [_ptr(a, (ny, nx), writable=True) if a is not None else (None, 1, None) for a in out]
+    if stream is None:
+        stream = _default_stream()
+    elif hasattr(stream, "cuda_stream"):
+        stream = stream.cuda_stream
+    cp = c_params(params)
+    _check(_lib.mrtfd_solve_noalloc(ctypes.byref(cp), _vp(int(stream)), *[_vp(p[0]) for p in ins], int(nsteps),
+                                    *[_vp(p[0]) if p[0] else None for p in outs]))
+    return out
+
+
 _lib.mrtfd_clock_stamp.argtypes = [_vp, _vp]
 
 
