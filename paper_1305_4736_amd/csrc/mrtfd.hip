@@ -682,7 +682,11 @@ int mrtfd_solve_noalloc(const mrtfd_params* p, void* hip_stream, const double* r
     if (rc) return rc;
     if (!rho || !ux || !uy || !T) return fail(MRTFD_EINVAL, "NULL input field");
     if (nsteps < 0) return fail(MRTFD_EINVAL, "nsteps < 0");
-    static_assert(sizeof(Blocks) <= 1024 && sizeof(StepArgs) <= 2048, "set-up area of the array too small");
+#if MARCH2_MFMA
+    return fail(MRTFD_EINVAL, "the no-allocation solve is not part of the matrix-core trial build");
+#endif
+    static_assert(MARCH2_MFMA || (sizeof(Blocks) <= 1024 && sizeof(StepArgs) <= 2048),
+                  "set-up area of the array too small");
     const Layout L = layout_of(*p);
     const size_t buf = (L.buf_bytes + 255) / 256 * 256;
     if (NOALLOC_HEAD + 2 * buf > NOALLOC_BYTES)

@@ -108,6 +108,14 @@ static bool build_blocks(double eta0, Blocks* out)
             B.IDd[r][c] = (double)(0.25L * IDd[r][c]);
         }
     for (int g = 0; g < 4; ++g) B.vmag[g] = (double)a[g];
+#if MARCH2_MFMA
+    for (int k = 0; k < NQ; ++k) {
+        double e[NQ] = {0.0}, m[NQ];
+        e[k] = 1.0;
+        moments(B, all_sums(e), m);
+        for (int i = 0; i < NQ; ++i) B.Md[i][k] = m[i];
+    }
+#endif
     return true;
 }
 

@@ -39,10 +39,20 @@ __host__ __device__ constexpr int sgy(int i)
 //   I0[g][c]  : S'_g from column c of (m_1, m_4, m_5, m_14)
 //   IX[g][c], IDa[g][c], IDd[g][c] likewise; the Y block is IX with its last
 //   column negated.
+// MARCH2_MFMA = 1 builds the matrix-core trial of the two-step kernel: its
+// second step takes the moments M f of a row as FP64 16 x 16 x 4 matrix
+// products from the ring (not bitwise equal to the other kernels; for
+// measurement only), reading the dense M kept in Md.
+#ifndef MARCH2_MFMA
+#define MARCH2_MFMA 0
+#endif
 struct Blocks {
     double F0[4][4], FX[4][4], FDa[2][2], FDd[2][2];
     double I0[4][4], IX[4][4], IDa[2][2], IDd[2][2];
     double vmag[4];     // |v_x| (= |v_y|) of a moving component, per group
+#if MARCH2_MFMA
+    double Md[NQ][NQ];  // dense M (row: moment, column: velocity)
+#endif
 };
 
 // Everything a step needs that is uniform over the grid.
@@ -54,6 +64,7 @@ struct StepArgs {
     double cx[4], cy[4];        // (1 - nu) / 2 per group and axis
     float nux32[4], nuy32[4];   // the same rounded to FP32 (FP32-storage convection)
     float cx32[4], cy32[4];
+    float cx32d[4], cy32d[4];   // 1 - nu in FP32 (the coefficient of the halved FP32 MC jump)
     double c8dt, c9dt;          // -dt (s_8 / s_5 - 1), -dt (s_9 / s_5 - 1); 0 when the correction is off
     double inv2dx, inv2dy;
     double side[4][4];          // (rho, ux, uy, T) of each side: equilibrium ghosts, walls
@@ -175,6 +186,22 @@ __host__ __device__ __forceinline__ void moments(const BT& B, const Sums& a, dou
     m[14] = fma(B.FDd[1][0], a.D[2], B.FDd[1][1] * a.D[3]);
 }
 
+// 1 / x from the hardware reciprocal estimate refined by two steps of
+// Newton's iteration r <- r + r (1 - x r), each of which squares the
+// relative error: about a third of the instructions of a correctly rounded
+// division, within an ulp of it.  Every kernel forms u = j / rho and
+// T = P / rho with it.
+__host__ __device__ __forceinline__ double recip(double x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+#else
+    return 1.0 / x;
+#endif
+}
+
 // Equilibria of all 16 moments (Appendix, closing equations) from the
 // conserved ones, R = 1, written with u = j / rho.  Returns P; eq[0..3] are
 // the conserved moments themselves.
@@ -184,7 +211,7 @@ __device__ __forceinline__ void equilibria(double rho, double ux, double uy, dou
     double ux2 = ux * ux, uy2 = uy * uy, u2 = ux2 + uy2;
     double ru2 = rho * u2;
     double rdu = rho * (ux2 - uy2);
-    double T = P / rho;
+    double T = P * recip(rho);
     eq[0] = rho;
     eq[1] = rho * ux;
     eq[2] = rho * uy;
@@ -305,7 +332,7 @@ __device__ __forceinline__ void macro_of(const BT& B, double inv_b, const double
     double jx = dot4(B.FX[0], a.X);
     double jy = dot4(B.FX[0], a.Y);
     double e = dot4(B.F0[1], a.S);
-    double ir = 1.0 / rho;
+    double ir = recip(rho);
     ux = jx * ir;
     uy = jy * ir;
     double P = (e - rho * (ux * ux + uy * uy)) * inv_b;
@@ -317,7 +344,7 @@ __device__ __forceinline__ void macro_of_cons(double inv_b, const double* c, dou
                                               double& T)
 {
     rho = c[0];
-    double ir = 1.0 / rho;
+    double ir = recip(rho);
     ux = c[1] * ir;
     uy = c[2] * ir;
     double P = (c[3] - rho * (ux * ux + uy * uy)) * inv_b;
@@ -327,7 +354,7 @@ __device__ __forceinline__ void macro_of_cons(double inv_b, const double* c, dou
 // Velocity from rho and j (neighbour ring of the correction).
 __device__ __forceinline__ void velocity_of_cons(double rho, double jx, double jy, double& ux, double& uy)
 {
-    double ir = 1.0 / rho;
+    double ir = recip(rho);
     ux = jx * ir;
     uy = jy * ir;
 }
@@ -345,11 +372,38 @@ __device__ __forceinline__ void velocity_of(const BT& B, const double* f, double
 // Limited jump psi(theta) * dn with theta = up / dn, in division-free and
 // branch-free form, equal to the printed piecewise limiter wherever theta is
 // defined and zero when the downstream jump vanishes:
-//   MC:     (sgn up + sgn dn) * min(|up|, |dn|, |up + dn| / 4)
-//   minmod: (sgn up + sgn dn) / 2 * min(|up|, |dn|)
-// (opposite signs give zero; a zero jump makes the minimum zero).  The MC
-// form is (sgn up + sgn dn) / 2 * min(2|up|, 2|dn|, |up + dn| / 2) with its
-// powers of two moved, which changes no bits.
+//   minmod: the one of up, dn nearer zero when they have the same sign, else
+//           zero -- the median of (0, up, dn);
+//   MC:     minmod(2 up, 2 dn, (up + dn) / 2)
+//           = 2 median(0, minmod(up, dn), (up + dn) / 4)
+//           = (sgn up + sgn dn) min(|up|, |dn|, |up + dn| / 4).
+// Every form picks one of the candidates and scales it by a power of two,
+// so all of them give the same value.  FP32 takes the median instruction and
+// returns MC halved (lim_scale below; the flux coefficient is doubled to
+// match, so the product is the same); FP64, which has no median, forms MC
+// as copysign(t, up) + copysign(t, dn) with t the minimum above (2 t with
+// the common sign, or 0) and minmod as max(min(up, dn), min(max(up, dn), 0)).
+// Its minima are written out as instructions: the IEEE-mode minimum of
+// operands the compiler cannot prove quiet (values moved across lanes or
+// carried round the loop) would otherwise first be quieted, one more
+// instruction each, for NaNs that a valid state never holds.
+template <int LIM, typename R>
+constexpr int lim_scale() { return (LIM == 0 && sizeof(R) == 4) ? 2 : 1; }
+
+__device__ __forceinline__ double min_abs3(double a, double b, double c)
+{
+    double t;   // min(|a|, |b|, c)
+    asm("v_min_f64 %0, |%1|, |%2|\n\tv_min_f64 %0, %0, %3" : "=&v"(t) : "v"(a), "v"(b), "v"(c));
+    return t;
+}
+__device__ __forceinline__ double median0(double a, double b)
+{
+    double lo, hi;   // max(min(a, b), min(max(a, b), 0))
+    asm("v_min_f64 %0, %2, %3\n\tv_max_f64 %1, %2, %3\n\tv_min_f64 %1, %1, 0\n\tv_max_f64 %0, %0, %1"
+        : "=&v"(lo), "=&v"(hi) : "v"(a), "v"(b));
+    return lo;
+}
+
 template <int LIM, typename R>
 __device__ __forceinline__ R limited(R up, R dn)
 {
@@ -357,13 +411,17 @@ __device__ __forceinline__ R limited(R up, R dn)
         return dn;
     } else if constexpr (LIM == 3) {    // first-order upwind
         return R(0);
-    } else {
-        const R h = copysign(R(1), up) + copysign(R(1), dn);
-        const R au = fabs(up), ad = fabs(dn);
+    } else if constexpr (sizeof(R) == 4) {
+        const float m = __builtin_amdgcn_fmed3f(0.0f, up, dn);
         if constexpr (LIM == 0)
-            return h * fmin(fmin(au, ad), R(0.25) * fabs(up + dn));
+            return __builtin_amdgcn_fmed3f(0.0f, m, 0.25f * (up + dn));   // half the MC jump
         else
-            return R(0.5) * h * fmin(au, ad);
+            return m;
+    } else if constexpr (LIM == 0) {
+        const R t = min_abs3(up, dn, R(0.25) * fabs(up + dn));
+        return copysign(t, up) + copysign(t, dn);
+    } else {
+        return median0(up, dn);
     }
 }
 
@@ -421,10 +479,12 @@ __device__ __forceinline__ R nu_of(const AT& a, int g)
     if constexpr (sizeof(R) == 8) return AX ? a.nuy[g] : a.nux[g];
     else return AX ? a.nuy32[g] : a.nux32[g];
 }
-template <typename R, int AX, class AT>
+// (times lim_scale: the coefficient of the limited jump as limited() returns it)
+template <typename R, int AX, int LIM, class AT>
 __device__ __forceinline__ R c_of(const AT& a, int g)
 {
     if constexpr (sizeof(R) == 8) return AX ? a.cy[g] : a.cx[g];
+    else if constexpr (lim_scale<LIM, R>() == 2) return AX ? a.cy32d[g] : a.cx32d[g];
     else return AX ? a.cy32[g] : a.cx32[g];
 }
 

@@ -367,9 +367,7 @@ __device__ __forceinline__ void step_tile(const T* __restrict__ fin, T* __restri
         if (keeps_cons<T>() && x >= -2 && x <= a.nx + 1 && y >= -2 && y <= a.ny + 1) cons_node(fin, a, x, y, c);
         node_moments<T>(*a.Bp, f, c, m, dc);
         rho = m[0];
-        const double ir = 1.0 / rho;
-        ux = m[1] * ir;
-        uy = m[2] * ir;
+        velocity_of_cons(rho, m[1], m[2], ux, uy);
         P = (m[3] - rho * (ux * ux + uy * uy)) * a.inv_b;
     }
     double dxux = 0.0, dxuy = 0.0, dyux = 0.0, dyuy = 0.0;
@@ -433,11 +431,11 @@ __device__ __forceinline__ void step_tile(const T* __restrict__ fin, T* __restri
         R acc = acc_start<T, R>(coll[i]);
         if (sgx(i) != 0) {
             const int sx = sgx(i);
-            acc = conv1<LIM, R>(acc, tb[c0 - 2 * sx], tb[c0 - sx], f0, tb[c0 + sx], nu_of<R, 0>(a, g), c_of<R, 0>(a, g));
+            acc = conv1<LIM, R>(acc, tb[c0 - 2 * sx], tb[c0 - sx], f0, tb[c0 + sx], nu_of<R, 0>(a, g), c_of<R, 0, LIM>(a, g));
         }
         if (!FLAT && sgy(i) != 0) {
             const int sy = sgy(i) * TW;
-            acc = conv1<LIM, R>(acc, tb[c0 - 2 * sy], tb[c0 - sy], f0, tb[c0 + sy], nu_of<R, 1>(a, g), c_of<R, 1>(a, g));
+            acc = conv1<LIM, R>(acc, tb[c0 - 2 * sy], tb[c0 - sy], f0, tb[c0 + sy], nu_of<R, 1>(a, g), c_of<R, 1, LIM>(a, g));
         }
         vd[i] = new_value<T, R>(f0, acc, coll[i]);
         fout[(long)i * a.plane + n0] = (T)vd[i];
@@ -570,7 +568,7 @@ __global__ void k_noneq(const T* __restrict__ f, int star, double* __restrict__ 
     load16(f, a, node(a, x, y), v);
     if constexpr (keeps_cons<T>()) cons_node(f, a, x, y, c);
     node_moments<T>(*a.Bp, v, c, m, dc);
-    const double rho = m[0], ir = 1.0 / rho, ux = m[1] * ir, uy = m[2] * ir;
+    const double rho = m[0], ir = recip(rho), ux = m[1] * ir, uy = m[2] * ir;
     const double P = (m[3] - rho * (ux * ux + uy * uy)) * a.inv_b;
     equilibria(rho, ux, uy, P, m[3], a.b, eq);
 #pragma unroll

@@ -162,12 +162,18 @@ __device__ __forceinline__ int source_of(int c, int n, int lo_kind, int hi_kind)
 __device__ __forceinline__ int source_ext(int c, int n, int lo_kind, int hi_kind)
 {
     if (c < 0) {
-        if (lo_kind == BC_PERIODIC) return ((c % n) + n) % n;
+        if (lo_kind == BC_PERIODIC) {   // c >= -4: at most four turns (n = 1)
+            while (c < 0) c += n;
+            return c;
+        }
         if (lo_kind == BC_OUTFLOW) return 0;
         return max(c, -2);
     }
     if (c >= n) {
-        if (hi_kind == BC_PERIODIC) return c % n;
+        if (hi_kind == BC_PERIODIC) {   // c <= n + 3
+            while (c >= n) c -= n;
+            return c;
+        }
         if (hi_kind == BC_OUTFLOW) return n - 1;
         return min(c, n + 1);
     }
@@ -197,6 +203,9 @@ constexpr int POUT = MW - 8;      // output columns of a pair's strip
 template <typename T>
 struct PairRing {
     T v[PRING][NQ][MW];
+#if MARCH2_MFMA
+    double mt[NQ][MW];   // matrix-core trial: a row's moments, moment-major
+#endif
 };
 template <>
 struct PairRing<float> {
@@ -251,21 +260,43 @@ __device__ __forceinline__ void ring_wall(CArgs& a, PairRing<T>* ring, int lane,
 }
 
 // One wavefront's walk through its band in direction DIR (+1: increasing y).
-// The window W holds four rows of all 16 planes: for output row j walked in
-// phase PH, slot PH & 3 holds row j - DIR, (PH + 1) & 3 row j, (PH + 2) & 3
-// row j + DIR, and (PH + 3) & 3 receives row j + 2 DIR, whose loads are
-// issued at the start of row j.  The next row is walked in phase PH + 1, so four
-// rows in phases 0..3 move the window by renaming alone; advance() moves it
-// by copies and keeps phase 0.
+// Output row j reads rows j, j + DIR and, for the planes whose y-upstream
+// side is ahead, j + 2 DIR.  The planes whose upstream side is behind need
+// the jump f_j - f_{j - DIR}, which is the jump the previous row took on its
+// downstream side (the same operands): it is carried, like each y face's
+// limited jump, so row j - DIR itself is not kept.  The window W holds three
+// rows of all 16 planes: for output row j walked in phase PH, slot PH % 3
+// holds row j, (PH + 1) % 3 row j + DIR, and (PH + 2) % 3 receives row
+// j + 2 DIR, whose loads are issued at the start of row j.  The next row is
+// walked in phase PH + 1, so three rows in phases 0..2 move the window by
+// renaming alone; advance() moves it by copies and keeps phase 0.  The
+// velocities U, V use the same slots, except that slot (PH + 2) % 3 holds
+// that of row j - DIR (for the central differences of the correction) until
+// row j + 2 DIR's replaces it at the end of row j.
 //
 // In a fused pair (ROLE_FIRST / ROLE_SECOND) the lanes of both wavefronts
 // are columns x0 + 56 s - 4 .. x0 + 56 s + 59 of strip s.  The first step
-// is valid on lanes 2..61, the second on lanes 4..59 (its output).
+// is valid on lanes 2..61, the second on lanes 4..59 (its output).  In
+// FP64 storage the second keeps no window: it reads rows j, j + DIR,
+// j + 2 DIR, and the neighbouring columns of row j, in the ring where the
+// first left them (LDS reads instead of register copies and lane moves).
 template <int LIM, typename T, int DIR, int ROLE = ROLE_SINGLE>
 struct Marcher {
     using R = conv_t<T>;   // convection precision
     using value_type = T;
     static constexpr int dir = DIR;
+    static constexpr int role = ROLE;
+    // ROLE_SECOND in FP64 storage reads its rows in the ring where they are
+    // used (DIRECT), and the neighbouring columns of a row too (LDS_X: two
+    // lane moves per double saved).  In FP32 storage the second wavefront
+    // copies each row from the ring into its window, as the first loads
+    // them, and takes lane moves: they fold into the subtraction that uses
+    // them, and reading in place cost more instructions than it saved.
+#ifndef MARCH2_DIRECT32
+#define MARCH2_DIRECT32 0
+#endif
+    static constexpr bool DIRECT = (ROLE == ROLE_SECOND) && (sizeof(T) == 8 || MARCH2_DIRECT32);
+    static constexpr bool LDS_X = DIRECT && sizeof(R) == 8;
 
     CArgs* argp;                      // kernel arguments
     __amdgpu_buffer_rsrc_t rin, rout;
@@ -273,20 +304,25 @@ struct Marcher {
     unsigned vout;                    // per-lane store offset, NO_STORE off the output columns
     PairRing<T>* ring;                // fused pair: the LDS ring
     int lane;                         // ROLE_FIRST: own lane; ROLE_SECOND: lane read from the ring
+    int laneL, laneR;                 // ROLE_SECOND: lanes read for the columns x - 1 and x + 1
     bool pass;                        // ROLE_FIRST: an equilibrium ghost column (value passes through)
     bool chk;                         // ROLE_FIRST: an interior column this wavefront checks
-    T W[4][NQ];                       // the window (see above)
-    double CW[4][4];                  // FP32 storage: conserved moments of each window row
-    double U[4], V[4];                // velocity (u_x, u_y) of each window row
+    T W[3][NQ];                       // the window (see above)
+    double CW[3][4];                  // FP32 storage: conserved moments of each window row
+    double U[3], V[3];                // velocity (u_x, u_y) of each window row, and of row j - DIR
     R carry[NQ];                      // limited jump of the y face carried from the previous row
+    R dcarry[NQ];                     // planes with sgy == DIR: the jump f_j - f_{j - DIR}
+#if MARCH2_MFMA
+    double Ma[4];                     // matrix-core trial: M[i][4 s + k] at lane i + 16 k, s = 0..3
+#endif
 
     __device__ __forceinline__ Marcher(CArgs* ap, const T* fin, T* fout, unsigned bytes, int x, bool out)
         : argp(ap),
           rin(__builtin_amdgcn_make_buffer_rsrc((void*)fin, (short)0, (int)bytes, BUF_WORD3)),
           rout(__builtin_amdgcn_make_buffer_rsrc((void*)fout, (short)0, (int)bytes, BUF_WORD3)),
           vin((unsigned)(source_of(min(x, ap->nx + 1), ap->nx, ap->bc[0], ap->bc[1]) + 2) * (unsigned)sizeof(T)),
-          vout(out ? (unsigned)(x + 2) * (unsigned)sizeof(T) : NO_STORE), ring(nullptr), lane(0), pass(false),
-          chk(false)
+          vout(out ? (unsigned)(x + 2) * (unsigned)sizeof(T) : NO_STORE), ring(nullptr), lane(0), laneL(0),
+          laneR(0), pass(false), chk(false)
     {
     }
 
@@ -302,13 +338,21 @@ struct Marcher {
             vin = (unsigned)(source_ext(x, nx, lo, hi) + 2) * (unsigned)sizeof(T);
             vout = NO_STORE;
             lane = l;
+            laneL = laneR = 0;
             pass = (x < 0 && lo == BC_EQUIL) || (x >= nx && hi == BC_EQUIL);
             chk = l >= 2 && l < MW - 2 && x >= ap->x0 && x < ap->x1;
         } else {
             vin = 0;
             const bool out = l >= 4 && l < MW - 4 && x < ap->x1;
             vout = out ? (unsigned)(x + 2) * (unsigned)sizeof(T) : NO_STORE;
-            lane = min(max(l + (source_out(x, nx, lo, hi) - x), 0), MW - 1);
+            // the lane holding column x + q's value (outflow ghost columns:
+            // the column they repeat), kept inside the strip
+            auto lane_of = [&](int q) {
+                return min(max(l + q + (source_out(x + q, nx, lo, hi) - (x + q)), 0), MW - 1);
+            };
+            lane = lane_of(0);
+            laneL = lane_of(-1);
+            laneR = lane_of(1);
             pass = false;
             chk = false;
         }
@@ -323,15 +367,43 @@ struct Marcher {
         asm volatile("" : "+s"(p));
         return *p;
     }
+    // The same, not before the value dep is computed: constants read
+    // through it are loaded when they are about to be used instead of at
+    // the top of the row, where they would be held (and spilled) meanwhile.
+    __device__ __forceinline__ CArgs& args_after(double dep) const
+    {
+        CArgs* p = argp;
+        asm volatile("" : "+s"(p) : "v"(dep));
+        return *p;
+    }
+
+    // ROLE_SECOND: the ring slot of row y of the first step's result
+    // (outflow ghost rows: the row they repeat).
+    __device__ __forceinline__ int rslot(int y, CArgs& a) const
+    {
+        const int ys = source_out(max(-2, min(y, a.ny + 1)), a.ny, a.bc[2], a.bc[3]);
+        return (ys + 4) & (PRING - 1);
+    }
+
+    // Population i and (FP32 storage) conserved moment k of the row in slot
+    // s: a window slot, or for ROLE_SECOND a ring slot.
+    __device__ __forceinline__ T pop(int s, int i) const
+    {
+        if (DIRECT) return ring->v[s][i][lane];
+        return W[s][i];
+    }
+    __device__ __forceinline__ double cons(int s, int k) const
+    {
+        if (DIRECT) return ring->c[s][k][lane];
+        return CW[s][k];
+    }
 
     __device__ __forceinline__ void load(T (&dst)[NQ], int y, CArgs& a) const
     {
         if (ROLE == ROLE_SECOND) {
-            // the first step's row (outflow ghost rows: the row they repeat)
-            const int ys = source_out(max(-2, min(y, a.ny + 1)), a.ny, a.bc[2], a.bc[3]);
-            const T(*src)[MW] = ring->v[(ys + 4) & (PRING - 1)];
+            const int sl = rslot(y, a);
 #pragma unroll
-            for (int i = 0; i < NQ; ++i) dst[i] = src[i][lane];
+            for (int i = 0; i < NQ; ++i) dst[i] = ring->v[sl][i][lane];
             return;
         }
         // rows beyond the ghost layers are only ever prefetched past a band's
@@ -349,8 +421,7 @@ struct Marcher {
     {
         if constexpr (keeps_cons<T>()) {
             if (ROLE == ROLE_SECOND) {
-                const int ys = source_out(max(-2, min(y, a.ny + 1)), a.ny, a.bc[2], a.bc[3]);
-                const int sl = (ys + 4) & (PRING - 1);
+                const int sl = rslot(y, a);
 #pragma unroll
                 for (int k = 0; k < 4; ++k) dst[k] = ring->c[sl][k][lane];
                 return;
@@ -371,74 +442,126 @@ struct Marcher {
         load_cons(CW[s], y, a);
     }
 
-    // Velocity of window row s: from its populations, or in FP32 storage
-    // from its stored conserved moments.
-    __device__ __forceinline__ void velocity(int s, CArgs& a)
+    // Velocity slot vs from the row in slot s (see pop()): from its
+    // populations, or in FP32 storage from its stored conserved moments.
+    __device__ __forceinline__ void velocity(int s, int vs, CArgs& a)
     {
         if constexpr (keeps_cons<T>()) {
-            velocity_of_cons(CW[s][0], CW[s][1], CW[s][2], U[s], V[s]);
+            velocity_of_cons(cons(s, 0), cons(s, 1), cons(s, 2), U[vs], V[vs]);
         } else {
             double g[NQ];
 #pragma unroll
-            for (int i = 0; i < NQ; ++i) g[i] = (double)W[s][i];
-            velocity_of(blocks_of(a), g, U[s], V[s]);
+            for (int i = 0; i < NQ; ++i) g[i] = (double)pop(s, i);
+            velocity_of(blocks_of(a), g, U[vs], V[vs]);
         }
     }
 
-    // Limited jump of the y face carried into the first output row j0 (the
-    // value the row before j0 would have left), in phase 0: W[3] = row
-    // j0 - 2 DIR, W[0] = j0 - DIR, W[1] = j0, W[2] = j0 + DIR.
-    __device__ __forceinline__ void start_carry()
+    // The jumps carried into output row j from rows j - 2 DIR (e), j - DIR
+    // (b), j (c) and j + DIR (d): what the row before j would have left.
+    __device__ __forceinline__ void start_carry(const T* e, const T* b, const T* c, const T* d)
     {
-        const T(&fB)[NQ] = W[0];
-        const T(&fC)[NQ] = W[1];
-        const T(&fD)[NQ] = W[2];
-        const T(&fE)[NQ] = W[3];
 #pragma unroll
         for (int i = 0; i < NQ; ++i) {
             const int sy = sgy(i);
-            if (sy == DIR)
-                carry[i] = limited<LIM, R>((R)fB[i] - (R)fE[i], (R)fC[i] - (R)fB[i]);
-            else if (sy == -DIR)
-                carry[i] = limited<LIM, R>((R)fC[i] - (R)fD[i], (R)fB[i] - (R)fC[i]);
+            if (sy == DIR) {
+                carry[i] = limited<LIM, R>((R)b[i] - (R)e[i], (R)c[i] - (R)b[i]);
+                dcarry[i] = (R)c[i] - (R)b[i];
+            } else if (sy == -DIR) {
+                carry[i] = limited<LIM, R>((R)c[i] - (R)d[i], (R)b[i] - (R)c[i]);
+            }
         }
     }
 
-    // New value of plane i at output row j, walked in phase PH.
-    template <int PH>
-    __device__ __forceinline__ double plane_value(int i, const double* coll, CArgs& a)
+#if MARCH2_MFMA
+    // Matrix-core trial (FP64 storage, second step of a pair): the moments
+    // of the row in ring slot sC as D = M F, F the 16 x 64 block of the row
+    // (velocity x column), in four 16-column blocks of four K = 4 products;
+    // F is read from the ring in operand layout (lane k' * 16 + c holds
+    // plane 4 s + k' of column 16 b + c), D leaves lane 16 q + c with moments
+    // 4 q .. 4 q + 3 of column 16 b + c and goes back to one column per lane
+    // through LDS.
+    typedef double double4_t __attribute__((ext_vector_type(4)));
+    __device__ __forceinline__ void mfma_load_a()
     {
-        const T(&fB)[NQ] = W[PH & 3];
-        const T(&fC)[NQ] = W[(PH + 1) & 3];
-        const T(&fD)[NQ] = W[(PH + 2) & 3];
-        const T(&fE)[NQ] = W[(PH + 3) & 3];
+        CArgs& a = args();
+        const double* Md = &((const Blocks*)a.Bp)->Md[0][0];
+        const int i = lane_id() & 15, k = lane_id() >> 4;
+#pragma unroll
+        for (int st = 0; st < 4; ++st) Ma[st] = Md[i * NQ + 4 * st + k];
+    }
+    __device__ __forceinline__ static int lane_id() { return (int)__lane_id(); }
+    __device__ __forceinline__ void mfma_moments(int sC, double* m)
+    {
+        const int l = lane_id(), c = l & 15, q = l >> 4;
+        double4_t d[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) d[b] = double4_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int st = 0; st < 4; ++st)
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                d[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(Ma[st], (double)ring->v[sC][4 * st + q][16 * b + c], d[b],
+                                                           0, 0, 0);
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) ring->mt[4 * q + r][16 * b + c] = d[b][r];
+        // this wavefront's own LDS writes, read back by other lanes: LDS
+        // keeps a wavefront's operations in order; the compiler must too
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) m[i] = ring->mt[i][lane];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+    }
+#endif
+
+    // New value of plane i at output row j; rows j, j + DIR, j + 2 DIR in
+    // slots sC, sD, sE (see pop()).
+    __device__ __forceinline__ double plane_value(int i, const double* coll, CArgs& a, int sC, int sD, int sE)
+    {
         const int g = i >> 2;
-        const R f0 = fC[i];
+        const R f0 = (R)pop(sC, i);
         R acc = acc_start<T, R>(coll[i]);
         const int sx = sgx(i), sy = sgy(i);
         if (sx != 0) {
-            const R fm1 = (sx > 0) ? lane_move<FROM_LEFT>(f0) : lane_move<FROM_RIGHT>(f0);
-            const R d1 = f0 - fm1;
-            // the downstream jump is the next lane's upstream one (same operands)
-            const R d2 = (sx > 0) ? lane_move<FROM_RIGHT>(d1) : lane_move<FROM_LEFT>(d1);
+            R d1, d2;
+            if (LDS_X) {
+                // the neighbouring columns from the ring (same operands as
+                // the lane moves below)
+                const R fl = (R)ring->v[sC][i][laneL], fr = (R)ring->v[sC][i][laneR];
+                d1 = f0 - ((sx > 0) ? fl : fr);
+                d2 = ((sx > 0) ? fr : fl) - f0;
+            } else {
+                const R fm1 = (sx > 0) ? lane_move<FROM_LEFT>(f0) : lane_move<FROM_RIGHT>(f0);
+                d1 = f0 - fm1;
+                // the downstream jump is the next lane's upstream one (same operands)
+                d2 = (sx > 0) ? lane_move<FROM_RIGHT>(d1) : lane_move<FROM_LEFT>(d1);
+            }
             const R l1 = limited<LIM, R>(d1, d2);
             const R l0 = (sx > 0) ? lane_move<FROM_LEFT>(l1) : lane_move<FROM_RIGHT>(l1);
-            acc = conv_add(acc, l1, l0, d1, nu_of<R, 0>(a, g), c_of<R, 0>(a, g));
+            acc = conv_add(acc, l1, l0, d1, nu_of<R, 0>(a, g), c_of<R, 0, LIM>(a, g));
         }
         if (sy != 0) {
             R d1, l1, l0;
-            if (sy == DIR) {        // upstream row is behind: its face value is carried
-                d1 = f0 - (R)fB[i];
-                l1 = limited<LIM, R>(d1, (R)fD[i] - f0);
+            if (sy == DIR) {        // upstream row is behind: its jump and face value are carried
+                d1 = dcarry[i];
+                const R d2 = (R)pop(sD, i) - f0;
+                l1 = limited<LIM, R>(d1, d2);
                 l0 = carry[i];
                 carry[i] = l1;
+                dcarry[i] = d2;
             } else {                // upstream row is ahead: needs row j + 2 DIR
-                d1 = f0 - (R)fD[i];
+                const R fd = (R)pop(sD, i);
+                d1 = f0 - fd;
                 l1 = carry[i];
-                l0 = limited<LIM, R>((R)fD[i] - (R)fE[i], d1);
+                l0 = limited<LIM, R>(fd - (R)pop(sE, i), d1);
                 carry[i] = l0;
             }
-            acc = conv_add(acc, l1, l0, d1, nu_of<R, 1>(a, g), c_of<R, 1>(a, g));
+            acc = conv_add(acc, l1, l0, d1, nu_of<R, 1>(a, g), c_of<R, 1, LIM>(a, g));
         }
         return new_value<T, R>(f0, acc, coll[i]);
     }
@@ -447,17 +570,33 @@ struct Marcher {
     template <int PH>
     __device__ __forceinline__ void row(int j)
     {
-        constexpr int B = PH & 3, C = (PH + 1) & 3, D = (PH + 2) & 3, E = (PH + 3) & 3;
+        constexpr int C = PH % 3, D = (PH + 1) % 3, E = (PH + 2) % 3;
         CArgs& a = args();
-        load_row(E, j + 2 * DIR, a);
+        int sC = C, sD = D, sE = E;
+        if (DIRECT) {
+            sC = rslot(j, a);
+            sD = rslot(j + DIR, a);
+            sE = rslot(j + 2 * DIR, a);
+        } else {
+            load_row(E, j + 2 * DIR, a);
+        }
 
         // moments, equilibria, correction and collision of row j
         double m[NQ], dc[4];
+#if MARCH2_MFMA
+        if constexpr (DIRECT && sizeof(T) == 8) {
+            mfma_moments(sC, m);
+        } else
+#endif
         {
-            double g[NQ];
+            double g[NQ], c[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int i = 0; i < NQ; ++i) g[i] = (double)W[C][i];
-            node_moments<T>(blocks_of(a), g, CW[C], m, dc);
+            for (int i = 0; i < NQ; ++i) g[i] = (double)pop(sC, i);
+            if constexpr (keeps_cons<T>()) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) c[k] = cons(sC, k);
+            }
+            node_moments<T>(blocks_of(a), g, c, m, dc);
         }
         const double rho = m[0];
         const double vx = U[C], vy = V[C];
@@ -467,15 +606,19 @@ struct Marcher {
         if (corr) {
             dxux = (lane_move<FROM_RIGHT>(vx) - lane_move<FROM_LEFT>(vx)) * a.inv2dx;
             dxuy = (lane_move<FROM_RIGHT>(vy) - lane_move<FROM_LEFT>(vy)) * a.inv2dx;
-            const double uxp = (DIR > 0) ? U[D] : U[B], uxm = (DIR > 0) ? U[B] : U[D];
-            const double uyp = (DIR > 0) ? V[D] : V[B], uym = (DIR > 0) ? V[B] : V[D];
+            // velocity slot E still holds row j - DIR
+            const double uxp = (DIR > 0) ? U[D] : U[E], uxm = (DIR > 0) ? U[E] : U[D];
+            const double uyp = (DIR > 0) ? V[D] : V[E], uym = (DIR > 0) ? V[E] : V[D];
             dyux = (uxp - uxm) * a.inv2dy;
             dyuy = (uyp - uym) * a.inv2dy;
         }
         const bool checked = (ROLE == ROLE_FIRST) ? (chk && j >= a.y0 && j < a.y1) : (vout != NO_STORE);
         if (checked && !(rho > 0.0 && P > 0.0)) atomicOr(a.flag, 1);
         double coll[NQ];
-        collision<keeps_cons<T>()>(a, blocks_of(a), m, rho, vx, vy, P, corr, dxux, dxuy, dyux, dyuy, dc, coll);
+        {
+            CArgs& ac = args_after(P);
+            collision<keeps_cons<T>()>(ac, blocks_of(ac), m, rho, vx, vy, P, corr, dxux, dxuy, dyux, dyuy, dc, coll);
+        }
 
         const unsigned base = (unsigned)((a.org - 2 + (long)j * a.pitch) * (long)sizeof(T));
         const unsigned pb = (unsigned)(a.plane * (long)sizeof(T));
@@ -494,7 +637,7 @@ struct Marcher {
 #pragma unroll
             for (int i = 0; i < NQ; ++i) {
                 if ((ps == 1) != (sgy(i) == -DIR)) continue;
-                vd[i] = plane_value<PH>(i, coll, a);
+                vd[i] = plane_value(i, coll, a, sC, sD, sE);
                 const T v = (T)vd[i];
                 if (ROLE == ROLE_FIRST)
                     dst[i][lane] = KEEP_SELECT ? (keep ? W[C][i] : v) : v;
@@ -518,15 +661,16 @@ struct Marcher {
         // FP64: the kept values overwrite the new ones afterwards, on the few
         // wavefronts that hold such a column or row, instead of a select per
         // plane (two per double) on every wavefront: 0.5-1 % faster; FP32
-        // (one select per plane, a larger kernel) keeps the select, which
-        // measured 1.4 % faster there
+        // (one select per plane, a larger kernel, the conserved moments
+        // selected too) keeps the select, which measured 12 % faster there
+        // (0.135 against 0.154 ms per step at 4096 x 1024)
         if (ROLE == ROLE_FIRST && !KEEP_SELECT && (__builtin_amdgcn_ballot_w64(pass) != 0 || keep_row)) {
             if (pass || keep_row) {
 #pragma unroll
                 for (int i = 0; i < NQ; ++i) dst[i][lane] = W[C][i];
             }
         }
-        velocity(E, a);
+        velocity(sE, E, a);
     }
 
     // ROLE_FIRST: row j of step n + 1 on a high wall side (k = 0: the wall
@@ -610,43 +754,63 @@ struct Marcher {
         }
     }
 
-    // Load the window of output row j in phase 0 (W[3] = row j - 2 DIR,
-    // W[0] = j - DIR, W[1] = j, W[2] = j + DIR) and the carried face jumps.
+    // The window, velocities and carried jumps of output row j in phase 0:
+    // rows j (slot 0) and j + DIR (slot 1); rows j - 2 DIR and j - DIR only
+    // for the carries and the velocity of j - DIR (velocity slot 2).
     __device__ __forceinline__ void prime(int j)
     {
-        {
-            CArgs& a = args();
-            load_row(3, j - 2 * DIR, a);
-            load_row(0, j - DIR, a);
-            load_row(1, j, a);
-            load_row(2, j + DIR, a);
-            velocity(0, a);
-            velocity(1, a);
-            velocity(2, a);
+        CArgs& a = args();
+        T e[NQ], b[NQ];
+#if MARCH2_MFMA
+        if constexpr (DIRECT && sizeof(T) == 8) mfma_load_a();
+#endif
+        if (DIRECT) {
+            const int s1 = rslot(j - DIR, a), s0 = rslot(j, a), sd = rslot(j + DIR, a);
+            load(e, j - 2 * DIR, a);
+            load(b, j - DIR, a);
+            velocity(s1, 2, a);
+            velocity(s0, 0, a);
+            velocity(sd, 1, a);
+            T c[NQ], d[NQ];
+            load(c, j, a);
+            load(d, j + DIR, a);
+            start_carry(e, b, c, d);
+        } else {
+            load(e, j - 2 * DIR, a);
+            load_row(2, j - DIR, a);
+            load_row(0, j, a);
+            load_row(1, j + DIR, a);
+            velocity(2, 2, a);
+            velocity(0, 0, a);
+            velocity(1, 1, a);
+#pragma unroll
+            for (int i = 0; i < NQ; ++i) b[i] = W[2][i];
+            start_carry(e, b, W[0], W[1]);
         }
-        start_carry();
     }
 
-    // Move the window one row on by copies (phase 0 before and after).
+    // Move the window one row on by copies (phase 0 before and after); the
+    // velocity of row j becomes that of the new row's j - DIR.
     __device__ __forceinline__ void advance()
     {
+        if (!DIRECT) {
 #pragma unroll
-        for (int i = 0; i < NQ; ++i) {
-            W[0][i] = W[1][i];
-            W[1][i] = W[2][i];
-            W[2][i] = W[3][i];
-        }
-        if constexpr (keeps_cons<T>()) {
+            for (int i = 0; i < NQ; ++i) {
+                W[0][i] = W[1][i];
+                W[1][i] = W[2][i];
+            }
+            if constexpr (keeps_cons<T>()) {
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                CW[0][k] = CW[1][k];
-                CW[1][k] = CW[2][k];
-                CW[2][k] = CW[3][k];
+                for (int k = 0; k < 4; ++k) {
+                    CW[0][k] = CW[1][k];
+                    CW[1][k] = CW[2][k];
+                }
             }
         }
+        const double u0 = U[0], v0 = V[0];
         U[0] = U[1]; V[0] = V[1];
         U[1] = U[2]; V[1] = V[2];
-        U[2] = U[3]; V[2] = V[3];
+        U[2] = u0; V[2] = v0;
     }
 
     // Output rows [yb, ye), walked from yb up (DIR > 0) or from ye - 1 down.
@@ -703,13 +867,13 @@ __global__ void __launch_bounds__(MW * MWPB, march_min_waves<T>()) k_march(const
     }
 }
 
-// Steady rows of a pair four at a time with the window moved by renaming:
-// FP32 storage 7 % faster (110.4 against 118.9 us per step at 4096 x 1024;
-// the compiler uses the register room it gains to load further ahead), FP64
-// 6 % slower (its registers run out: 256 with spills, and the kernel's code
-// outgrows the instruction cache).
+// Steady rows of a pair three at a time with the window moved by renaming
+// (phases 0..2), or one at a time with copies.  (With the former four-row
+// window, renaming made FP32 storage 7 % faster -- 110.4 against 118.9 us
+// per step at 4096 x 1024 -- and FP64 6 % slower: its registers ran out,
+// 256 with spills, and the kernel's code outgrew the instruction cache.)
 #ifndef MARCH2_RENAME64
-#define MARCH2_RENAME64 0
+#define MARCH2_RENAME64 1
 #endif
 #ifndef MARCH2_RENAME32
 #define MARCH2_RENAME32 1
@@ -725,7 +889,7 @@ __device__ __forceinline__ void pair_sync()
 }
 
 // n rows of a pair's steady part from row j on, one barrier after each:
-// four rows per trip in phases 0..3 (the window moves by renaming) where
+// three rows per trip in phases 0..2 (the window moves by renaming) where
 // that is faster, the rest in phase 0 with copies.
 template <class M>
 __device__ __forceinline__ void pair_rows(M& m, int j, int n)
@@ -734,16 +898,14 @@ __device__ __forceinline__ void pair_rows(M& m, int j, int n)
     constexpr bool rename = (sizeof(typename M::value_type) == 8) ? MARCH2_RENAME64 : MARCH2_RENAME32;
     int k = 0;
     if (rename) {
-        for (; k + 4 <= n; k += 4) {
+        for (; k + 3 <= n; k += 3) {
             m.template row<0>(j);
             pair_sync();
             m.template row<1>(j + DIR);
             pair_sync();
             m.template row<2>(j + 2 * DIR);
             pair_sync();
-            m.template row<3>(j + 3 * DIR);
-            pair_sync();
-            j += 4 * DIR;
+            j += 3 * DIR;
         }
     }
     for (; k < n; ++k) {
@@ -757,11 +919,12 @@ __device__ __forceinline__ void pair_rows(M& m, int j, int n)
 // The walk of a pair through output rows [yb, ye) (H rows) in direction
 // DIR, in H + 6 barrier-separated iterations; r(k) = row of march position
 // k.  The first wavefront makes rows r(-2) .. r(H + 1) of step n + 1 at
-// iterations 0..3 and 5..H+4; the second loads its window r(-2) .. r(1)
-// at iteration 4 and makes row r(k) of step n + 2 at iteration k + 6,
-// reading r(k + 2), which the first finished one iteration before.  A ring
-// slot is rewritten three iterations after it was last read at the
-// earliest (outflow ghost rows read the last interior row).
+// iterations 0..3 and 5..H+4; the second reads r(-2) .. r(1) at
+// iteration 4 (its carried jumps and velocities) and makes row r(k) of
+// step n + 2 at iteration k + 6 from rows r(k) .. r(k + 2) in the ring, the
+// last of which the first finished one iteration before.  A ring slot is
+// rewritten at the iteration after it was last read at the earliest
+// (outflow ghost rows read the last interior row).
 //
 // Walls along y (DIR > 0 only): the second step needs the wall rows of step
 // n + 1 as the refill after a step leaves them.  On the high side the first

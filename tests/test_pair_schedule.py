@@ -4,9 +4,12 @@ The kernel's two wavefronts advance in lockstep, one barrier per iteration,
 through H + 6 iterations for a band of H output rows; r(k) is the row at
 march position k.  The first wavefront makes rows r(-2) .. r(1) at
 iterations 0..3 and r(2) .. r(H + 1) at iterations 5..H + 4 into a ring of
-four rows (row y in slot (y + 4) mod 4); the second loads r(-2) .. r(1) at
-iteration 4 and, at iteration k + 6, reads r(k + 2) and makes output row
-r(k).  Outflow ghost rows are read at the row they repeat.
+four rows (row y in slot (y + 4) mod 4); the second reads r(-2) .. r(1) at
+iteration 4 and, at iteration k + 6, reads r(k), r(k + 1) and r(k + 2) and
+makes output row r(k) (in FP64 storage it reads its rows where it uses them;
+in FP32 storage it copies r(k + 2) into registers then, having read r(k) and
+r(k + 1) at the two iterations before: a subset of the same reads).  Outflow
+ghost rows are read at the row they repeat.
 
 Walls along y (bands walk up only): the rows the first step makes at a
 wall's node row and ghost row are not valid; on the high side the first
@@ -69,7 +72,7 @@ def replay(ny, lo, hi, yb, ye, d):
         second[3] = [("r", 1)] + [("w", w, True) for w in (0, -1) if w >= yb - 2]
     second[4] = [("r", source_out(r(k), ny, lo, hi)) for k in (-2, -1, 0, 1)]
     for t in range(6, H + 6):
-        second[t] = [("r", source_out(r(t - 4), ny, lo, hi))]
+        second[t] = [("r", source_out(r(t - q), ny, lo, hi)) for q in (6, 5, 4)]
 
     for t in range(H + 6):
         touched = {}
