@@ -105,7 +105,10 @@ def kernel_hash() -> str:
 
 
 def algorithmic_bytes_per_node(precision: str) -> int:
-    return 32 * (8 if precision == "fp64" else 4)
+    """State bytes read and written per node-update: 16 populations in FP64
+    (2 x 128 B), or in FP32 storage 16 FP32 populations and 4 FP64
+    conserved moments (2 x 96 B)."""
+    return 256 if precision == "fp64" else 192
 
 
 def run_gpu(case, steps, warmup, noneq_every, log, per_launch=0, keep_macros=False):
@@ -205,7 +208,7 @@ def roofline(res, precision):
     dispatch) against the VALU peak, and HBM traffic (FETCH_SIZE +
     WRITE_SIZE) against 8 TB/s.  `bound` is the roof the kernel is closer to;
     `achieved`/`peak`/`frac` are that roof's.  The algorithmic HBM rate (256
-    or 128 bytes per node-update, two node-updates per node with two steps
+    or 192 bytes per node-update, two node-updates per node with two steps
     per launch) is reported beside it as `hbm_effective`."""
     k = res["steps_per_launch"]
     bytes_launch = algorithmic_bytes_per_node(precision) * res["nodes"] * k
@@ -363,7 +366,9 @@ def run_batched(steps, warmup, log, n=512):
     log(f"[bench] batched {n} instances, {nodes} nodes: {ms / steps:.4f} ms/step, {value:.4e} node-updates/s")
     return {"workload": f"riemann_batch_{n}", "instances": n, "nodes": nodes, "precision": "fp32",
             "limiter": "mc", "steps": steps, "ms_per_step": ms / steps, "value": value,
-            "unit": "node-updates/s", "screen_redraws": redraws, "nonfinite_instances": nonfinite,
+            "unit": "node-updates/s",
+            "screen": {"T_ratio_max": W.SCREEN[0], "p_ratio_max": W.SCREEN[1], "mach_max": W.SCREEN[2]},
+            "screen_redraws": redraws, "nonfinite_instances": nonfinite,
             "autotune_us_per_unit": dict(zip(names, map(float, costs))),
             "shape_classes": shapes}
 
@@ -389,8 +394,9 @@ def run_served(rate, seconds, log, drain, label, steps_per_tick=50, capacity=409
 
 
 PROFILE_KERNELS = {"k_march2/fp64": "k_march2<0, double>", "k_march/fp64": "k_march<0, double>",
-                   "k_march2/fp32": "k_march2<0, float>", "k_march/fp32": "k_march<0, float>"}
-PROFILE_COMMAND = ("python3 bench.py --steps 20 --warmup 4 --no-cpu-baseline --no-limiters --no-batched "
+                   "k_march2/fp32": "k_march2<0, float>", "k_march/fp32": "k_march<0, float>",
+                   "k_march2_batch/fp32": "k_march2_batch<0, float>", "k_march_batch/fp32": "k_march_batch<0, float>"}
+PROFILE_COMMAND = ("python3 bench.py --steps 20 --warmup 4 --no-cpu-baseline --no-limiters "
                    "--no-serve --pmc-copy-calibration")
 
 
@@ -454,15 +460,18 @@ def summarize_profile(fetch_dir, write_dir, sq_dir, out_path):
         if f is None or w is None:
             continue
         fb, wb = 1024 * f * fetch_factor, 1024 * w * write_factor
-        k = 2 if kname == "k_march2" else 1
-        alg = algorithmic_bytes_per_node(prec) * nodes * k
+        k = 2 if kname.startswith("k_march2") else 1
+        # (the batched launches' node counts vary from launch to launch: no
+        # algorithmic count per launch for them)
+        alg = None if kname.endswith("_batch") else algorithmic_bytes_per_node(prec) * nodes * k
         kernels[key] = {"instance": inst, "dispatches": {"fetch": nf, "write": nw, "sq": nv},
                         "fetch_bytes_per_launch": round(fb), "write_bytes_per_launch": round(wb),
                         "hbm_bytes_per_launch": round(fb + wb), "algorithmic_bytes_per_launch": alg,
-                        "hbm_over_algorithmic": round((fb + wb) / alg, 4),
+                        "hbm_over_algorithmic": round((fb + wb) / alg, 4) if alg else None,
                         "valu_insts_per_launch": v, "waves_per_launch": wv, "valu_insts_per_wave": v / wv if wv else None,
                         "grbm_gui_active_per_launch": g}
-    out = {"workload": "shock_interface_4096x1024", "kernel_hash": kernel_hash(),
+    out = {"workload": "shock_interface_4096x1024 (single-grid kernels), riemann_batch_512 (batched)",
+           "kernel_hash": kernel_hash(),
            "command": PROFILE_COMMAND, "passes": ["FETCH_SIZE", "WRITE_SIZE", "SQ_INSTS_VALU SQ_WAVES GRBM_GUI_ACTIVE"],
            "copy_calibration": {"bytes": int(gib), "fetch_factor": fetch_factor, "write_factor": write_factor},
            "kernels": kernels}

@@ -477,9 +477,9 @@ struct Marcher {
     // of the row in ring slot sC as D = M F, F the 16 x 64 block of the row
     // (velocity x column), in four 16-column blocks of four K = 4 products;
     // F is read from the ring in operand layout (lane k' * 16 + c holds
-    // plane 4 s + k' of column 16 b + c), D leaves lane 16 q + c with moments
-    // 4 q .. 4 q + 3 of column 16 b + c and goes back to one column per lane
-    // through LDS.
+    // plane 4 s + k' of column 16 b + c), D leaves register r of lane
+    // 16 q + c with moment q + 4 r of column 16 b + c (the layout measured
+    // on gfx950) and goes back to one column per lane through LDS.
     typedef double double4_t __attribute__((ext_vector_type(4)));
     __device__ __forceinline__ void mfma_load_a()
     {
@@ -505,7 +505,7 @@ struct Marcher {
 #pragma unroll
         for (int b = 0; b < 4; ++b)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) ring->mt[4 * q + r][16 * b + c] = d[b][r];
+            for (int r = 0; r < 4; ++r) ring->mt[q + 4 * r][16 * b + c] = d[b][r];
         // this wavefront's own LDS writes, read back by other lanes: LDS
         // keeps a wavefront's operations in order; the compiler must too
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");

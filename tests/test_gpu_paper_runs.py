@@ -5,24 +5,26 @@
   Rankine-Hugoniot speed puts it, and the paper's statement that the
   Lax-Wendroff scheme oscillates strongly behind the shock while the limiter
   does not (total variation of rho);
-* Sec. IV-B, Lax tube (gamma = 1.4, dx = 0.003, dt = 1e-5) against the exact
-  Riemann solution at t = 0.14, and against the oracle over its first 500
-  steps.  At these rates (s_5..7 = 2e3 against 1e5 for the other
-  non-conserved moments) and at the hot left state (T = 7.9) the discrete
-  model is linearly unstable at high wavenumber, so rounding-level seeds
-  grow:
+* Sec. IV-B, Lax tube (gamma = 1.4, dx = 0.003, dt = 1e-5) against the
+  oracle over its first 500 steps, and against the exact Riemann solution
+  at t = 0.14 and at the paper's t = 0.45 (45 000 steps).  At these rates
+  (s_5..7 = 2e3 against 1e5 for the other non-conserved moments) and at
+  the hot left state (T = 7.9) the discrete model amplifies some
+  rounding-level perturbations:
   - a transverse mode: in exact arithmetic a flow uniform in y keeps
     u_y = 0.  The GPU path keeps it exactly (its factored M^-1 is
-    mirror-symmetric to the last bit); the oracle's M^-1, from Gauss-Jordan
-    elimination, is not, so the oracle seeds the mode (u_y ~ 1e-13 after
-    500 steps, 1e-2 after 3000);
-  - a longitudinal mode at the inflow boundary: the collision residual of
-    an equilibrium state is a few ulps on the GPU (exactly zero in the
-    oracle at this state), so interior nodes drift against the fixed inflow
-    ghosts; the seed grows to 4e-6 in T after 15000 steps and ends the GPU
-    run near step 25000 (the oracle's seed is 1e8 smaller and lasts past the
-    paper's t = 0.45).
-  Hence the short oracle window, the exact u_y = 0 check and t = 0.14;
+    mirror-symmetric to the last bit, checked); the oracle's M^-1, from
+    Gauss-Jordan elimination, is not, so the oracle seeds the mode (u_y ~
+    1e-13 after 500 steps, 1e-2 after 3000), hence the oracle window of
+    500 steps;
+  - at the inflow boundary the uniform left state must not drift against
+    the fixed inflow ghosts: a separate test holds that state alone between
+    equilibrium ghosts for 20 000 steps and bounds its change (a few ulps,
+    no growth).  With it the GPU run holds to t = 0.45: relative L1 errors
+    against the exact solution of 1.9 % / 0.41 % / 1.4 % (rho / p / u) at
+    t = 0.14 and 3.0 % / 0.50 % / 0.96 % at t = 0.45, the oracle's own run
+    giving the same to two digits; the growth of the density error is the
+    contact's smearing;
 * Sec. V, the heavy/light shock interaction (1200 x 10 cells, gamma = 2,
   t = 0.3) against the oracle over its first 1000 steps, the wave positions of
   the exact solution, and the paper's statements about Delta* on the centre
@@ -120,24 +122,53 @@ def test_lax_tube_vs_exact_and_oracle(lib, orc):
     fo = orc.run(c["params"], c["rho"], c["ux"], c["uy"], c["T"], 500)
     assert_parity(mg, orc.macros(c["params"], fo), TOL["fp64"], g, "lax 500 steps")
 
-    n, t = 14000, 0.14
-    print(f"[paper] lax tube 1000x1 {n} steps vs exact", flush=True)
-    mg, _ = gpu_run(lib, c, n)
-    x = (np.arange(1000) + 0.5) * 0.003
-    ex_r, ex_u, ex_p = sample(left, right, g, (x - 1.5) / t)
-    assert np.all(mg[2] == 0.0)               # no transverse velocity, to the last bit
-    r, u = mg[0][0], mg[1][0]
-    p = r * mg[3][0]
-    assert np.abs(r - ex_r).sum() / np.abs(ex_r).sum() < 0.03
-    assert np.abs(p - ex_p).sum() / np.abs(ex_p).sum() < 0.01
-    assert np.abs(u - ex_u).sum() / np.abs(ex_u).sum() < 0.025
-    # the transmitted shock where the exact solution has it (within 3 cells)
-    ps, us = star_state(left, right, g)
-    rr, ur, pr = right
-    cr = math.sqrt(g * pr / rr)
-    shock = 1.5 + t * (ur + cr * math.sqrt((g + 1) / (2 * g) * ps / pr + (g - 1) / (2 * g)))
-    xs = x[500 + np.argmax(np.abs(np.diff(p[500:])))] + 0.0015
-    assert abs(xs - shock) <= 3 * 0.003
+    # against the exact solution at t = 0.14 and at the paper's t = 0.45
+    # (45 000 steps; the rarefaction head then reaches the inflow side).
+    # Relative L1 bars: rho 3 % at 0.14 and 3.5 % at 0.45 -- the density
+    # error is that of the contact, which the scheme keeps smearing (the
+    # oracle's own run: 1.9 % and 3.0 %) -- p 1 %, u 2.5 %.
+    for n, t, rho_bar in ((14000, 0.14, 0.03), (45000, 0.45, 0.035)):
+        print(f"[paper] lax tube 1000x1 {n} steps vs exact", flush=True)
+        mg, _ = gpu_run(lib, c, n)
+        x = (np.arange(1000) + 0.5) * 0.003
+        ex_r, ex_u, ex_p = sample(left, right, g, (x - 1.5) / t)
+        assert np.all(mg[2] == 0.0)               # no transverse velocity, to the last bit
+        r, u = mg[0][0], mg[1][0]
+        p = r * mg[3][0]
+        er = np.abs(r - ex_r).sum() / np.abs(ex_r).sum()
+        ep = np.abs(p - ex_p).sum() / np.abs(ex_p).sum()
+        eu = np.abs(u - ex_u).sum() / np.abs(ex_u).sum()
+        print(f"[paper] lax tube t = {t}: L1 rho {er:.4f}, p {ep:.4f}, u {eu:.4f}", flush=True)
+        assert er < rho_bar and ep < 0.01 and eu < 0.025, (t, er, ep, eu)
+        # the transmitted shock where the exact solution has it (within 3 cells)
+        ps, us = star_state(left, right, g)
+        rr, ur, pr = right
+        cr = math.sqrt(g * pr / rr)
+        shock = 1.5 + t * (ur + cr * math.sqrt((g + 1) / (2 * g) * ps / pr + (g - 1) / (2 * g)))
+        xs = x[500 + np.argmax(np.abs(np.diff(p[500:])))] + 0.0015
+        assert abs(xs - shock) <= 3 * 0.003, (t, xs, shock)
+
+
+def test_lax_left_state_stays_put(lib):
+    # the Lax tube's hot left state alone, with equilibrium ghosts at the same
+    # state on both sides: in exact arithmetic a fixed point of the step.  On
+    # the GPU it must stay within rounding of its start and not drift (a
+    # drift here is what would seed the boundary mode of the tube)
+    left = (0.445, 0.698, 0.445 * 7.928)
+    c = W.riemann_1d(left, left, 1.4, 256, ny=1, length=0.768, x0=0.384, s=W.rates(1e5, 2e3, 1e3, 1e5),
+                     limiter="mc", nsteps=20000, name="lax_left")
+    c["params"]["dt"] = 1e-5
+    dev = []
+    with lib.Solver(c["params"]) as s:
+        s.init(c["rho"], c["ux"], c["uy"], c["T"])
+        m0 = s.macros()
+        for _ in range(4):
+            s.step(5000)
+            s.sync()
+            m = s.macros()
+            dev.append(max(float(np.abs(a - b).max() / np.abs(b).max()) for a, b in zip(m, m0) if np.abs(b).max() > 0))
+    print(f"[paper] lax left state, largest relative change after 5000..20000 steps: {dev}", flush=True)
+    assert max(dev) < 1e-13 and dev[-1] <= 2.0 * dev[0] + 1e-14, dev
 
 
 def test_heavy_light_noneq_characteristics(lib, orc):

@@ -1,8 +1,9 @@
 """GPU test of the serving loop (continuous batching).
 
 A small stream of requests of different kinds (Riemann quadrants, thermal
-Couette flows), grid sizes, step counts and precisions is served with
-requests joining while others are running and slots being reused.  Each
+Couette flows), grid sizes, step counts and precisions is served, under
+each admission policy, with requests joining while others are running and
+slots being reused.  Each
 served result must equal the same request run alone (bitwise, the per-node
 arithmetic does not depend on the mix) and match the FP64 oracle (1e-11
 relative for FP64 storage, 2e-5 for FP32 storage).
@@ -37,13 +38,16 @@ def small_stream(n=14, seed=5):
     return out
 
 
-def test_served_results_equal_alone_and_oracle(lib, orc):
+@pytest.mark.parametrize("policy", ["fifo", "latency"])
+def test_served_results_equal_alone_and_oracle(lib, orc, policy):
     mrtfd, serve = lib
     reqs = small_stream()
-    # capacity 3 per precision: later requests wait for slots and reuse them
-    with serve.Server(capacity=3, steps_per_tick=7, keep_results=True, reserve_bytes=0) as srv:
+    # capacity 3 per precision: later requests wait for slots and reuse them;
+    # the latency policy admits smallest work first within its bound
+    with serve.Server(capacity=3, steps_per_tick=7, keep_results=True, reserve_bytes=0, policy=policy) as srv:
         rep = srv.run(reqs, realtime=True)
     assert rep["completed"] == len(reqs) and rep["backlog"] == 0
+    assert rep["failed"] == 0 and rep["shed"] == 0
     assert rep["max_active"] <= 6 and rep["ticks"] > 3
     assert np.isfinite(rep["p50_s"]) and rep["p99_s"] >= rep["p50_s"]
     for i, (t, spec) in enumerate(reqs):
