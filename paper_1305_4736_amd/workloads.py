@@ -200,15 +200,21 @@ def paper_heavy_light(precision="fp64"):
 # Batched Riemann instances (512 by default)
 
 # Stability envelope of the 16-velocity model with the rates below: states
-# are redrawn until both the pressure and the temperature ratios across the
-# problem stay within SCREEN_RATIO and every initial state is subsonic
-# (strong shocks, cold regions and supersonic states beyond these drive f
-# to negative temperatures within a few hundred steps, in the oracle and on
-# the GPU alike).
+# are redrawn until the temperature and the pressure ratios across the
+# problem stay within bounds and every initial state is subsonic (strong
+# shocks, cold regions and supersonic states beyond these drive some node to
+# a negative temperature, in the oracle and on the GPU alike).  A screen is
+# (temperature ratio, pressure ratio, Mach number) bounds.  The batch takes
+# the widest screen found under which none of its 512 draws has a node with
+# rho <= 0, T <= 0 or a non-finite value after any of its 1000 steps in the
+# oracle: temperature ratio 5, pressure ratio 7, subsonic (291 redraws).
+# tests/golden/make_screen_envelope.py counts the failing draws under this
+# and twelve other screens: every wider one tried has some (a temperature
+# ratio of 20 alone: 58 of 512).  The four-quadrant requests of the served
+# stream keep ratios of 5.
 SCREEN_RATIO = 5.0
 SCREEN_MACH = 1.0
-# (temperature ratio, pressure ratio, Mach number) bounds of a screen
-SCREEN = (SCREEN_RATIO, SCREEN_RATIO, SCREEN_MACH)
+SCREEN = (SCREEN_RATIO, 7.0, SCREEN_MACH)
 
 
 def riemann_batch(n=512, seed=13054736, nsteps=1000, precision="fp32", screen=SCREEN):
