@@ -367,9 +367,9 @@ struct Marcher {
         asm volatile("" : "+s"(p));
         return *p;
     }
-    // The same, not before the value dep is computed: constants read
-    // through it are loaded when they are about to be used instead of at
-    // the top of the row, where they would be held (and spilled) meanwhile.
+    // The same, not before the value dep is computed (the collision reads
+    // its constants through it; measured against reading them through
+    // args(): the same instructions and scalar spills).
     __device__ __forceinline__ CArgs& args_after(double dep) const
     {
         CArgs* p = argp;
