@@ -276,27 +276,31 @@ __device__ __forceinline__ void ring_wall(CArgs& a, PairRing<T>* ring, int lane,
 //
 // In a fused pair (ROLE_FIRST / ROLE_SECOND) the lanes of both wavefronts
 // are columns x0 + 56 s - 4 .. x0 + 56 s + 59 of strip s.  The first step
-// is valid on lanes 2..61, the second on lanes 4..59 (its output).  In
-// FP64 storage the second keeps no window: it reads rows j, j + DIR,
-// j + 2 DIR, and the neighbouring columns of row j, in the ring where the
-// first left them (LDS reads instead of register copies and lane moves).
+// is valid on lanes 2..61, the second on lanes 4..59 (its output).  The
+// second copies its rows from the ring where the first left them.
 template <int LIM, typename T, int DIR, int ROLE = ROLE_SINGLE>
 struct Marcher {
     using R = conv_t<T>;   // convection precision
     using value_type = T;
     static constexpr int dir = DIR;
     static constexpr int role = ROLE;
-    // ROLE_SECOND in FP64 storage reads its rows in the ring where they are
-    // used (DIRECT), and the neighbouring columns of a row too (LDS_X: two
-    // lane moves per double saved).  In FP32 storage the second wavefront
-    // copies each row from the ring into its window, as the first loads
-    // them, and takes lane moves: they fold into the subtraction that uses
-    // them, and reading in place cost more instructions than it saved.
-#ifndef MARCH2_DIRECT32
-#define MARCH2_DIRECT32 0
+    // ROLE_SECOND copies each row from the ring into its window, as the
+    // first step loads them from HBM, and takes the neighbouring columns by
+    // lane moves.  Measured alternatives, same boxes: reading the rows in
+    // the ring where they are used (DIRECT; no window copies) 7-8 % slower
+    // in FP64 (0.140-0.142 against 0.131-0.133 ms per step; the reads sit
+    // on each row's critical path) and more instructions in FP32; reading
+    // the FP64 neighbouring columns in the ring instead of two lane moves
+    // per double (LDS_X) 2.5 % fewer VALU instructions per wavefront but
+    // 3 % slower (0.136-0.139 ms).
+#ifndef MARCH2_DIRECT
+#define MARCH2_DIRECT 0
 #endif
-    static constexpr bool DIRECT = (ROLE == ROLE_SECOND) && (sizeof(T) == 8 || MARCH2_DIRECT32);
-    static constexpr bool LDS_X = DIRECT && sizeof(R) == 8;
+#ifndef MARCH2_LDS_X64
+#define MARCH2_LDS_X64 0
+#endif
+    static constexpr bool DIRECT = (ROLE == ROLE_SECOND) && MARCH2_DIRECT;
+    static constexpr bool LDS_X = (ROLE == ROLE_SECOND) && sizeof(R) == 8 && MARCH2_LDS_X64;
 
     CArgs* argp;                      // kernel arguments
     __amdgpu_buffer_rsrc_t rin, rout;
@@ -520,8 +524,9 @@ struct Marcher {
 #endif
 
     // New value of plane i at output row j; rows j, j + DIR, j + 2 DIR in
-    // slots sC, sD, sE (see pop()).
-    __device__ __forceinline__ double plane_value(int i, const double* coll, CArgs& a, int sC, int sD, int sE)
+    // slots sC, sD, sE (see pop()), row j in ring slot rC (ROLE_SECOND).
+    __device__ __forceinline__ double plane_value(int i, const double* coll, CArgs& a, int sC, int sD, int sE,
+                                                  int rC)
     {
         const int g = i >> 2;
         const R f0 = (R)pop(sC, i);
@@ -532,7 +537,7 @@ struct Marcher {
             if (LDS_X) {
                 // the neighbouring columns from the ring (same operands as
                 // the lane moves below)
-                const R fl = (R)ring->v[sC][i][laneL], fr = (R)ring->v[sC][i][laneR];
+                const R fl = (R)ring->v[rC][i][laneL], fr = (R)ring->v[rC][i][laneR];
                 d1 = f0 - ((sx > 0) ? fl : fr);
                 d2 = ((sx > 0) ? fr : fl) - f0;
             } else {
@@ -573,8 +578,9 @@ struct Marcher {
         constexpr int C = PH % 3, D = (PH + 1) % 3, E = (PH + 2) % 3;
         CArgs& a = args();
         int sC = C, sD = D, sE = E;
+        const int rC = (ROLE == ROLE_SECOND) ? rslot(j, a) : 0;
         if (DIRECT) {
-            sC = rslot(j, a);
+            sC = rC;
             sD = rslot(j + DIR, a);
             sE = rslot(j + 2 * DIR, a);
         } else {
@@ -637,7 +643,7 @@ struct Marcher {
 #pragma unroll
             for (int i = 0; i < NQ; ++i) {
                 if ((ps == 1) != (sgy(i) == -DIR)) continue;
-                vd[i] = plane_value(i, coll, a, sC, sD, sE);
+                vd[i] = plane_value(i, coll, a, sC, sD, sE, rC);
                 const T v = (T)vd[i];
                 if (ROLE == ROLE_FIRST)
                     dst[i][lane] = KEEP_SELECT ? (keep ? W[C][i] : v) : v;

@@ -6,10 +6,10 @@ march position k.  The first wavefront makes rows r(-2) .. r(1) at
 iterations 0..3 and r(2) .. r(H + 1) at iterations 5..H + 4 into a ring of
 four rows (row y in slot (y + 4) mod 4); the second reads r(-2) .. r(1) at
 iteration 4 and, at iteration k + 6, reads r(k), r(k + 1) and r(k + 2) and
-makes output row r(k) (in FP64 storage it reads its rows where it uses them;
-in FP32 storage it copies r(k + 2) into registers then, having read r(k) and
-r(k + 1) at the two iterations before: a subset of the same reads).  Outflow
-ghost rows are read at the row they repeat.
+makes output row r(k) (it copies r(k + 2) into registers then, and in FP64
+reads the neighbouring columns of r(k) again; the variant that reads every
+row where it is used needs all three).  Outflow ghost rows are read at the
+row they repeat.
 
 Walls along y (bands walk up only): the rows the first step makes at a
 wall's node row and ghost row are not valid; on the high side the first
