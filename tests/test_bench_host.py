@@ -49,7 +49,8 @@ def test_roofline_takes_the_nearer_roof(monkeypatch, tmp_path):
     assert r["bound"] == "alu" and abs(r["frac"] - 1.2e8 / 0.25e-3 / bench.VALU_PEAK) < 1e-3
     assert abs(r["hbm_measured"]["frac"] - 0.5) < 1e-3
     assert abs(r["hbm_effective"]["GBs"] - 2 * 256 * 4096 * 1024 / 0.25e-3 / 1e9) < 0.1
-    assert abs(r["valu"]["frac_at_measured_clock"] - r["frac"] * 2400 / 2000) < 1e-3
+    # the clock estimate is reported, nothing is derived from it
+    assert r["core_clock_mhz_estimate"] == 2000.0 and set(r["valu"]) == {"insts_per_launch", "per_s", "frac"}
     # with few VALU instructions the HBM roof is the nearer one
     ctr["kernels"]["k_march2/fp64"]["valu_insts_per_launch"] = 1.0e7
     f.write_text(json.dumps(ctr))
