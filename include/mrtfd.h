@@ -214,12 +214,14 @@ int mrtfd_solve_noalloc(const mrtfd_params* p, void* hip_stream, const double* r
 
 /* Diagnostics: enqueue on hip_stream (a hipStream_t) a kernel of one block
  * per XCD that writes, to the device array out[16], each XCD's shader-clock
- * counter (core clock cycles; out[2 x]) and the constant-rate 100 MHz
- * counter (out[2 x + 1]), x the XCD number.  Two stamps around a stretch of
- * launches give the core clock each XCD ran at: cycles / (ticks / 1e8)
- * (the clock counters of different XCDs are not aligned; pairs a stamp did
- * not write keep their old contents).  Asynchronous; read out after the
- * stream has finished. */
+ * counter (s_memtime; out[2 x]) and real-time counter (s_memrealtime, taken
+ * as 100 MHz; out[2 x + 1]), x the XCD number.  Two stamps around a
+ * stretch of launches estimate the clock each XCD ran at as
+ * counts / (ticks / 1e8) (the counters of different XCDs are not aligned;
+ * pairs a stamp did not write keep their old contents).  The estimate
+ * follows the clock's changes within a run but has read above the 2.4 GHz
+ * maximum on some machines: it is not an exact core clock.  Asynchronous;
+ * read out after the stream has finished. */
 int mrtfd_clock_stamp(void* hip_stream, unsigned long long* out);
 
 /* Host-only: the dense 16x16 M and M^-1 (row-major) the kernels use in their

@@ -39,10 +39,10 @@ __host__ __device__ constexpr int sgy(int i)
 //   I0[g][c]  : S'_g from column c of (m_1, m_4, m_5, m_14)
 //   IX[g][c], IDa[g][c], IDd[g][c] likewise; the Y block is IX with its last
 //   column negated.
-// MARCH2_MFMA = 1 (with MARCH2_DIRECT = 1) builds the matrix-core trial of
-// the two-step kernel: its second step takes the moments M f of a row as
-// FP64 16 x 16 x 4 matrix products from the ring (not bitwise equal to the
-// other kernels; for measurement only), reading the dense M kept in Md.
+// MARCH2_MFMA = 1 builds the matrix-core trial of the two-step kernel: its
+// second step takes the moments M f of a row as FP64 16 x 16 x 4 matrix
+// products from the ring (not bitwise equal to the other kernels; for
+// measurement only), reading the dense M kept in Md.
 #ifndef MARCH2_MFMA
 #define MARCH2_MFMA 0
 #endif

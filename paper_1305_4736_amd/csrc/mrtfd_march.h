@@ -590,8 +590,8 @@ struct Marcher {
         // moments, equilibria, correction and collision of row j
         double m[NQ], dc[4];
 #if MARCH2_MFMA
-        if constexpr (DIRECT && sizeof(T) == 8) {
-            mfma_moments(sC, m);
+        if constexpr (ROLE == ROLE_SECOND && sizeof(T) == 8) {
+            mfma_moments(rC, m);
         } else
 #endif
         {
@@ -768,7 +768,7 @@ struct Marcher {
         CArgs& a = args();
         T e[NQ], b[NQ];
 #if MARCH2_MFMA
-        if constexpr (DIRECT && sizeof(T) == 8) mfma_load_a();
+        if constexpr (ROLE == ROLE_SECOND && sizeof(T) == 8) mfma_load_a();
 #endif
         if (DIRECT) {
             const int s1 = rslot(j - DIR, a), s0 = rslot(j, a), sd = rslot(j + DIR, a);
