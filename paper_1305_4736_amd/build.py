@@ -25,6 +25,10 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}",
          # a * b + c is fused only within one source expression, so every
          # kernel that shares a device function rounds it the same way
          "-ffp-contract=on",
+         # device code flushes denormals (FP32 and FP64), which lets the
+         # limiter scale by an instruction's output modifier; the host part
+         # keeps the default
+         "-Xarch_device", "-fdenormal-fp-math=preserve-sign",
          "-Wall", "-Wno-unused-function"]
 
 

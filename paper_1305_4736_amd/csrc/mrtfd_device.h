@@ -64,7 +64,10 @@ struct StepArgs {
     double cx[4], cy[4];        // (1 - nu) / 2 per group and axis
     float nux32[4], nuy32[4];   // the same rounded to FP32 (FP32-storage convection)
     float cx32[4], cy32[4];
-    float cx32d[4], cy32d[4];   // 1 - nu in FP32 (the coefficient of the halved FP32 MC jump)
+    // coefficients of the MC jump as limited() returns it (scaled by 4 in
+    // FP64, by 2 in FP32): (1 - nu) / 8 in FP64, (1 - nu) / 4 in FP32
+    double cxq[4], cyq[4];
+    float cx32h[4], cy32h[4];
     double c8dt, c9dt;          // -dt (s_8 / s_5 - 1), -dt (s_9 / s_5 - 1); 0 when the correction is off
     double inv2dx, inv2dy;
     double side[4][4];          // (rho, ux, uy, T) of each side: equilibrium ghosts, walls
@@ -378,23 +381,47 @@ __device__ __forceinline__ void velocity_of(const BT& B, const double* f, double
 //           = 2 median(0, minmod(up, dn), (up + dn) / 4)
 //           = (sgn up + sgn dn) min(|up|, |dn|, |up + dn| / 4).
 // Every form picks one of the candidates and scales it by a power of two,
-// so all of them give the same value.  FP32 takes the median instruction and
-// returns MC halved (lim_scale below; the flux coefficient is doubled to
-// match, so the product is the same); FP64, which has no median, forms MC
-// as copysign(t, up) + copysign(t, dn) with t the minimum above (2 t with
-// the common sign, or 0) and minmod as max(min(up, dn), min(max(up, dn), 0)).
-// Its minima are written out as instructions: the IEEE-mode minimum of
-// operands the compiler cannot prove quiet (values moved across lanes or
-// carried round the loop) would otherwise first be quieted, one more
-// instruction each, for NaNs that a valid state never holds.
-template <int LIM, typename R>
-constexpr int lim_scale() { return (LIM == 0 && sizeof(R) == 4) ? 2 : 1; }
-
-__device__ __forceinline__ double min_abs3(double a, double b, double c)
+// so all of them give the same value up to that power.  MC is returned
+// scaled (lim_exp below: by 4 in FP64, by 2 in FP32) and the flux
+// coefficient is scaled down to match, so the product is the same to the
+// bit; the scaling is the output modifier of an instruction the limiter
+// issues anyway, which saves the quarter of (up + dn) per face:
+//   FP64: 4 t = min(4 min(|up|, |dn|), |up + dn|), returned as
+//         copysign(4 t, up) + copysign(4 t, dn) (8 t with the common
+//         sign, or 0);
+//   FP32: med3(0, 4 med3(0, up, dn), up + dn) = 2 MC.
+// FP64 minmod is max(min(up, dn), min(max(up, dn), 0)).  The FP64 minima
+// are written as instructions: the IEEE-mode minimum of operands the
+// compiler cannot prove quiet (values moved across lanes or carried round
+// the loop) would otherwise first be quieted, one more instruction each,
+// for NaNs that a valid state never holds.  The output modifier applies
+// only with denormals flushed, which the library is built with (its
+// populations, moments and their differences never come near the
+// denormal range), and with the IEEE mode bit clear (convect_mode).
+// Output modifiers apply only while the wave's IEEE mode bit is clear, so
+// every kernel that convects clears it on entry (the bit belongs to the
+// wave and is set again for the next launch).  With it clear, minimum and
+// maximum treat NaN operands differently (no quieting first); arithmetic,
+// comparisons and therefore the unphysical-node check are unchanged.
+__device__ __forceinline__ void convect_mode()
 {
-    double t;   // min(|a|, |b|, c)
-    asm("v_min_f64 %0, |%1|, |%2|\n\tv_min_f64 %0, %0, %3" : "=&v"(t) : "v"(a), "v"(b), "v"(c));
+    asm volatile("s_setreg_imm32_b32 hwreg(HW_REG_MODE, 9, 1), 0\n\ts_nop 3" ::: "memory");
+}
+
+template <int LIM, typename R>
+constexpr int lim_exp() { return (LIM == 0) ? (sizeof(R) == 8 ? 2 : 1) : 0; }
+
+__device__ __forceinline__ double min_abs3_x4(double a, double b, double c)
+{
+    double t;   // min(4 min(|a|, |b|), |c|)
+    asm("v_min_f64 %0, |%1|, |%2| mul:4\n\tv_min_f64 %0, %0, |%3|" : "=&v"(t) : "v"(a), "v"(b), "v"(c));
     return t;
+}
+__device__ __forceinline__ float med3_0_x4(float a, float b)
+{
+    float m;    // 4 med3(0, a, b)
+    asm("v_med3_f32 %0, 0, %1, %2 mul:4" : "=v"(m) : "v"(a), "v"(b));
+    return m;
 }
 __device__ __forceinline__ double median0(double a, double b)
 {
@@ -412,13 +439,12 @@ __device__ __forceinline__ R limited(R up, R dn)
     } else if constexpr (LIM == 3) {    // first-order upwind
         return R(0);
     } else if constexpr (sizeof(R) == 4) {
-        const float m = __builtin_amdgcn_fmed3f(0.0f, up, dn);
         if constexpr (LIM == 0)
-            return __builtin_amdgcn_fmed3f(0.0f, m, 0.25f * (up + dn));   // half the MC jump
+            return __builtin_amdgcn_fmed3f(0.0f, med3_0_x4(up, dn), up + dn);   // twice the MC jump
         else
-            return m;
+            return __builtin_amdgcn_fmed3f(0.0f, up, dn);
     } else if constexpr (LIM == 0) {
-        const R t = min_abs3(up, dn, R(0.25) * fabs(up + dn));
+        const R t = min_abs3_x4(up, dn, up + dn);                               // 4 times the MC jump
         return copysign(t, up) + copysign(t, dn);
     } else {
         return median0(up, dn);
@@ -479,13 +505,18 @@ __device__ __forceinline__ R nu_of(const AT& a, int g)
     if constexpr (sizeof(R) == 8) return AX ? a.nuy[g] : a.nux[g];
     else return AX ? a.nuy32[g] : a.nux32[g];
 }
-// (times lim_scale: the coefficient of the limited jump as limited() returns it)
+// (over 2^lim_exp: the coefficient of the limited jump as limited() returns it)
 template <typename R, int AX, int LIM, class AT>
 __device__ __forceinline__ R c_of(const AT& a, int g)
 {
-    if constexpr (sizeof(R) == 8) return AX ? a.cy[g] : a.cx[g];
-    else if constexpr (lim_scale<LIM, R>() == 2) return AX ? a.cy32d[g] : a.cx32d[g];
-    else return AX ? a.cy32[g] : a.cx32[g];
+    static_assert(lim_exp<LIM, R>() == 0 || lim_exp<LIM, R>() == (sizeof(R) == 8 ? 2 : 1), "coefficient table");
+    if constexpr (sizeof(R) == 8) {
+        if constexpr (lim_exp<LIM, R>() == 2) return AX ? a.cyq[g] : a.cxq[g];
+        else return AX ? a.cy[g] : a.cx[g];
+    } else {
+        if constexpr (lim_exp<LIM, R>() == 1) return AX ? a.cy32h[g] : a.cx32h[g];
+        else return AX ? a.cy32[g] : a.cx32[g];
+    }
 }
 
 template <int LIM, typename R>

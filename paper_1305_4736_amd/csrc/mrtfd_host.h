@@ -147,8 +147,10 @@ inline StepArgs make_args(const mrtfd_params& p, const Layout& L, const Blocks& 
         a.nuy32[g] = (float)a.nuy[g];
         a.cx32[g] = (float)a.cx[g];
         a.cy32[g] = (float)a.cy[g];
-        a.cx32d[g] = 2.0f * a.cx32[g];
-        a.cy32d[g] = 2.0f * a.cy32[g];
+        a.cxq[g] = 0.25 * a.cx[g];
+        a.cyq[g] = 0.25 * a.cy[g];
+        a.cx32h[g] = 0.5f * a.cx32[g];
+        a.cy32h[g] = 0.5f * a.cy32[g];
     }
     a.correction = p.energy_flux_correction ? 1 : 0;
     a.c8dt = a.correction ? -p.dt * (p.s[7] / p.s[4] - 1.0) : 0.0;

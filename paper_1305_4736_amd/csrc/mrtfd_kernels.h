@@ -463,6 +463,7 @@ __global__ void __launch_bounds__(TXW * BYR, 1) k_step(const T* __restrict__ fin
                                                       StepArgs a)
 {
     __shared__ TileSmem<T, TXW, BYR> sm_;
+    convect_mode();
     const int bid = blockIdx.x;
     const int t = (bid & 7) * a.per_xcd + (bid >> 3);
     if (t >= a.ntx * a.nty) return;
@@ -698,6 +699,7 @@ __global__ void __launch_bounds__(TXW * BYR, 1) k_step_batch(const BatchSlot* __
                                                             const int* __restrict__ list, int nlist, long L)
 {
     __shared__ TileSmem<T, TXW, BYR, FLAT> sm_;
+    convect_mode();
     const int nitems = prefix[nlist];
     for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
         int lo = 0, hi = nlist;

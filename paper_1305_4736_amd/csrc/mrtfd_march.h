@@ -850,6 +850,7 @@ template <int LIM, typename T>
 __global__ void __launch_bounds__(MW * MWPB, march_min_waves<T>()) k_march(const T* __restrict__ fin, T* __restrict__ fout,
                                                     const StepArgs* __restrict__ ap)
 {
+    convect_mode();
     CArgs& a = *(CArgs*)ap;
     // the wavefront index is uniform across the wavefront: say so, so that
     // band, strip and row offsets live in scalar registers
@@ -1016,6 +1017,7 @@ __global__ void __launch_bounds__(2 * MW, MARCH2_MINW) k_march2(const T* __restr
                                                           const StepArgs* __restrict__ ap)
 {
     __shared__ PairRing<T> ring;
+    convect_mode();
     CArgs& a = *(CArgs*)ap;
     const int role = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / MW)), lane = threadIdx.x % MW;
     const int bid = blockIdx.x;
@@ -1115,6 +1117,7 @@ __global__ void __launch_bounds__(MW * MWPB) k_march_batch(const BatchSlot* __re
                                                           const int* __restrict__ prefix,
                                                           const int* __restrict__ list, int nlist, long L, long R)
 {
+    convect_mode();
     const MRTFD_CONSTANT BatchSlot* cs = (const MRTFD_CONSTANT BatchSlot*)slots;
     const MRTFD_CONSTANT int* cpre = (const MRTFD_CONSTANT int*)prefix;
     const MRTFD_CONSTANT int* clist = (const MRTFD_CONSTANT int*)list;
@@ -1192,6 +1195,7 @@ __global__ void __launch_bounds__(2 * MW, MARCH2_MINW) k_march2_batch(const Batc
                                                                   long R)
 {
     __shared__ PairRing<T> ring;
+    convect_mode();
     const MRTFD_CONSTANT BatchSlot* cs = (const MRTFD_CONSTANT BatchSlot*)slots;
     const MRTFD_CONSTANT int* cpre = (const MRTFD_CONSTANT int*)prefix;
     const MRTFD_CONSTANT int* clist = (const MRTFD_CONSTANT int*)list;

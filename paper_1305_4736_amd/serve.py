@@ -295,8 +295,10 @@ class Server:
         if self.policy == "latency":
             report.update({"latency_target_s": self.latency_target, "shed_after_s": self.shed_after,
                            "measured_rate": rate})
+        # indices into the stream: failures are few and named in every
+        # report; shed requests can run to thousands
+        report["failed_requests"] = sorted(failed)
         if self.keep_results:
             report["results"] = results
-            report["failed_requests"] = sorted(failed)
             report["shed_requests"] = sorted(shed)
         return report
