@@ -34,6 +34,162 @@
 
 using namespace mrtfd;
 
+// The batched strip kernels (they use the single-instance march's row
+// walk and pair schedule).
+namespace {
+
+// Rows per band of a batched instance: short bands balance the static
+// assignment of items to wavefronts over instances of mixed sizes (8-12
+// rows measured best on a 512-instance mix; 32 rows cost 19 % more).
+#ifndef MARCH_BROWS
+#define MARCH_BROWS 12
+#endif
+constexpr int MBROWS = MARCH_BROWS;
+
+// Band layout of a batched instance: bands of at most MBROWS rows.
+inline void set_march_rows(StepArgs& a, int rows)
+{
+    const int ex = a.x1 - a.x0, ey = a.y1 - a.y0;
+    a.m_nsx = (ex + MOUT - 1) / MOUT;
+    a.m_rows = std::max(1, std::min(rows, ey));
+    a.m_nby = (ey + a.m_rows - 1) / a.m_rows;
+    a.m_per_xcd = 0;
+}
+
+// Batched form: persistent wavefronts stride over the (band, strip) items
+// of the listed slots, numbered slot after slot (prefix[k] = first item of
+// list[k]); wavefront g of the launch takes items g, g + G, ... where the
+// wavefronts of each XCD are numbered contiguously (the grid is a multiple
+// of 8 blocks).  The step and round counters L and R decide each slot's
+// current buffer and whether it still steps, as in the tile form.
+template <int LIM, typename T>
+__global__ void __launch_bounds__(MW * MWPB) k_march_batch(const BatchSlot* __restrict__ slots,
+                                                          const int* __restrict__ prefix,
+                                                          const int* __restrict__ list, int nlist, long L, long R)
+{
+    convect_mode();
+    const MRTFD_CONSTANT BatchSlot* cs = (const MRTFD_CONSTANT BatchSlot*)slots;
+    const MRTFD_CONSTANT int* cpre = (const MRTFD_CONSTANT int*)prefix;
+    const MRTFD_CONSTANT int* clist = (const MRTFD_CONSTANT int*)list;
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / MW)), lane = threadIdx.x % MW;
+    const int nb = gridDim.x, bid = blockIdx.x;
+    const int g = ((bid & 7) * (nb >> 3) + (bid >> 3)) * MWPB + w;
+    const int G = nb * MWPB;
+    const int nitems = cpre[nlist];
+    for (int item = g; item < nitems; item += G) {
+        int lo = 0, hi = nlist;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (cpre[mid] <= item) lo = mid;
+            else hi = mid;
+        }
+        const MRTFD_CONSTANT BatchSlot& sl = cs[clist[lo]];
+        if (L >= sl.stop) continue;
+        CArgs& a = sl.a;
+        const int par = (int)(((sl.pair ? R : L) - sl.pstart) & 1);
+        const T* fin = (const T*)sl.buf[par];
+        T* fout = (T*)sl.buf[par ^ 1];
+        const int r = item - cpre[lo];
+        const int band = r / a.m_nsx, strip = r - band * a.m_nsx;
+        const int x = a.x0 + strip * MOUT - 2 + lane;
+        const bool out = lane >= 2 && lane < MW - 2 && x < a.x1;
+        const int yb = a.y0 + band * a.m_rows, ye = min(yb + a.m_rows, a.y1);
+        const unsigned bytes = (unsigned)(a.elems * (long)sizeof(T));
+        if (MARCH_ALTERNATE && (band & 1)) {
+            Marcher<LIM, T, -1> mr(&a, fin, fout, bytes, x, out);
+            mr.walk(yb, ye);
+            mr.refill_walls(yb, ye);
+        } else {
+            Marcher<LIM, T, 1> mr(&a, fin, fout, bytes, x, out);
+            mr.walk(yb, ye);
+            mr.refill_walls(yb, ye);
+        }
+    }
+}
+
+}  // namespace
+
+namespace {
+
+// Rows per pair band of a batched instance (the shortest of the heights
+// fit_pair_rows chooses from), and the fewest rows an instance needs to take
+// two steps per launch in the batch (with items dealt out in slot order, by
+// a stride, 32 / 8 beat bands of 16, 24, 48 and 64 rows and minimums of 1,
+// 4, 16 and 32 by 1-7 % on the 512-instance Riemann mix).
+#ifndef MARCH2_BROWS
+#define MARCH2_BROWS 32
+#endif
+#ifndef MARCH2_BATCH_MIN_ROWS
+#define MARCH2_BATCH_MIN_ROWS 8
+#endif
+constexpr int MBROWS2 = MARCH2_BROWS;
+
+// Pair-band layout of a batched instance: bands of at most MBROWS2 rows.
+inline void set_pair_rows(StepArgs& a, int rows)
+{
+    const int ex = a.x1 - a.x0, ey = a.y1 - a.y0;
+    a.p_nsx = (ex + POUT - 1) / POUT;
+    a.p_rows = std::max(1, std::min(rows, ey));
+    a.p_nby = (ey + a.p_rows - 1) / a.p_rows;
+    a.p_per_xcd = 0;
+}
+
+// Batched two-step form: persistent blocks (one pair each) take the
+// (band, strip) items of the listed pair slots.  The list holds runs of
+// bands of one slot (list[e] the slot, band[e] its first band, prefix[e]
+// the run's first item), ordered by band height, tallest first (the host's
+// order, rebuild_lists); item i of a run is band band[e] + i / strips,
+// strip i % strips.  Block g (numbered XCD-aware as in k_march_batch) takes
+// item g of each pass of nb items on even passes and item nb - 1 - g on
+// odd ones, so that the shorter items at the end even out the blocks'
+// totals.  Every listed slot has two steps left (the caller's rule), and
+// its current buffer is the parity of R.  Both wavefronts of a block take
+// the same items, so they pass the same number of barriers.
+template <int LIM, typename T>
+__global__ void __launch_bounds__(2 * MW, MARCH2_MINW) k_march2_batch(const BatchSlot* __restrict__ slots,
+                                                                  const int* __restrict__ prefix,
+                                                                  const int* __restrict__ list,
+                                                                  const int* __restrict__ band0, int nlist, long L,
+                                                                  long R)
+{
+    __shared__ PairRing<T> ring;
+    convect_mode();
+    const MRTFD_CONSTANT BatchSlot* cs = (const MRTFD_CONSTANT BatchSlot*)slots;
+    const MRTFD_CONSTANT int* cpre = (const MRTFD_CONSTANT int*)prefix;
+    const MRTFD_CONSTANT int* clist = (const MRTFD_CONSTANT int*)list;
+    const MRTFD_CONSTANT int* cband = (const MRTFD_CONSTANT int*)band0;
+    const int role = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / MW)), lane = threadIdx.x % MW;
+    const int nb = gridDim.x, bid = blockIdx.x;
+    const int g = (bid & 7) * (nb >> 3) + (bid >> 3);
+    const int nitems = cpre[nlist];
+    int odd = 0;
+    for (int base = 0; base < nitems; base += nb, odd ^= 1) {
+        const int item = base + (odd ? nb - 1 - g : g);
+        if (item >= nitems) continue;
+        int lo = 0, hi = nlist;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (cpre[mid] <= item) lo = mid;
+            else hi = mid;
+        }
+        const MRTFD_CONSTANT BatchSlot& sl = cs[clist[lo]];
+        if (L + 1 >= sl.stop) continue;      // (not listed by the caller) both wavefronts skip
+        CArgs& a = sl.a;
+        const int par = (int)((R - sl.pstart) & 1);
+        const T* fin = (const T*)sl.buf[par];
+        T* fout = (T*)sl.buf[par ^ 1];
+        const int r = item - cpre[lo];
+        const int rb = r / a.p_nsx, strip = r - rb * a.p_nsx;
+        const int band = cband[lo] + rb;
+        const int x = a.x0 + strip * POUT - 4 + lane;
+        const int yb = a.y0 + band * a.p_rows, ye = min(yb + a.p_rows, a.y1);
+        const unsigned bytes = (unsigned)(a.elems * (long)sizeof(T));
+        pair_walk<LIM, T, 1>(role, a, fin, fout, bytes, x, lane, yb, ye, &ring);
+    }
+}
+
+}  // namespace
+
 namespace {
 
 constexpr int NSHAPE = 5;
@@ -95,13 +251,16 @@ struct mrtfd_batch_s {
     BatchSlot* d_slot;
     Blocks* d_blocks;
     int* d_flags;
-    int* d_lists;                       // NLIST x (capacity + 1) prefixes, then NLIST x capacity slot lists, then walls
+    int* d_lists;                       // NLIST x (capacity + 1) prefixes, then NLIST x capacity slot lists, then
+                                        // capacity walls, then the two-step list: 2 capacity + 1 prefixes,
+                                        // 2 capacity slots, 2 capacity first bands
     int nlist[NLIST], nwall;
     bool dirty;
     long L;                             // steps taken by the batch
     long R;                             // rounds (one or two steps each)
     long rounds1, rounds2;              // one-step and two-step rounds run (diagnostics)
     int mrows;                          // band height of the strip slots' one-step launches
+    int prows;                          // band height of the strip slots' two-step launches
     bool fit_rows;                      // fit mrows to the load (off for calibration batches)
     std::vector<long> rstop;            // R at which a pair slot stopped stepping (LONG_MAX while it steps)
     int per_launch;                     // 2: two-step rounds where possible; 1: one step per round
@@ -125,6 +284,11 @@ namespace {
 int* prefix_dev(mrtfd_batch_s* B, int s) { return B->d_lists + s * (B->capacity + 1); }
 int* list_dev(mrtfd_batch_s* B, int s) { return B->d_lists + NLIST * (B->capacity + 1) + s * B->capacity; }
 int* wall_dev(mrtfd_batch_s* B) { return B->d_lists + NLIST * (B->capacity + 1) + NLIST * B->capacity; }
+// the two-step list: up to two runs per slot (its full bands, its shorter last band)
+size_t pair_region_ints(int capacity) { return 3 * (size_t)(2 * capacity) + 1; }
+int* pair_prefix_dev(mrtfd_batch_s* B) { return wall_dev(B) + B->capacity; }
+int* pair_list_dev(mrtfd_batch_s* B) { return pair_prefix_dev(B) + 2 * B->capacity + 1; }
+int* pair_band_dev(mrtfd_batch_s* B) { return pair_list_dev(B) + 2 * B->capacity; }
 
 int check_slot(mrtfd_batch_s* B, int k)
 {
@@ -194,7 +358,7 @@ void set_args(mrtfd_batch_s* B, int k)
     const ShapeDef& sd = SHAPES[s == MARCH ? 0 : s];
     B->slot[k].a = make_args(B->prm[k], B->lay[k], B->blk[k], B->d_blocks + k, B->d_flags + k, sd.txw, sd.byr, 1 << 20);
     set_march_rows(B->slot[k].a, B->mrows);
-    set_pair_rows(B->slot[k].a, MBROWS2);
+    set_pair_rows(B->slot[k].a, B->prows);
     B->slot[k].pair = pair_capable(B, k) ? 1 : 0;
 }
 
@@ -265,14 +429,68 @@ int fit_march_rows(mrtfd_batch_s* B)
     return MRTFD_OK;
 }
 
+// Band height of the two-step launches: the tallest of 160, 128, 96, 80,
+// 64, 48 and 32 rows that still gives the resident pairs PAIR_ITEMS_PER_PAIR
+// items each, so that the balanced order (rebuild_lists) evens them out.
+// Taller bands walk fewer halo rows per output row, and a light batch keeps
+// 32-row bands, whose launches are shortest.  Growing takes 1.25 times the
+// items, so a load near a threshold does not flip heights; a change
+// re-uploads the descriptors of the occupied slots in one copy.  Measured
+// on the 512-instance Riemann mix (FP32 storage, ms per step, fixed
+// heights): 24 rows 0.917, 32 0.890, 40 0.856, 48 0.838, 56 0.840, 64
+// 0.827, 80 0.805, 112 0.815, 160 0.796, 256 0.828 (10, 7.7 and 6.7 items
+// per pair at 80, 160 and 256 rows); on 20 s of the served stream, fixed
+// 80-row bands against 32 raised the overloaded stream's achieved rate
+// from 3.00e10 to 3.27e10 node-updates/s but the median latency at 25 and
+// 15 requests/s from 0.63 to 0.95 s and from 0.14 to 0.26 s.
+#ifndef PAIR_ITEMS_PER_PAIR
+#define PAIR_ITEMS_PER_PAIR 8
+#endif
+int fit_pair_rows(mrtfd_batch_s* B)
+{
+    if (!B->fit_rows) return MRTFD_OK;
+    const long need = (long)PAIR_ITEMS_PER_PAIR * B->pair_blocks;
+    const int levels[] = {5 * MBROWS2, 4 * MBROWS2, 3 * MBROWS2, 5 * MBROWS2 / 2, 2 * MBROWS2, 3 * MBROWS2 / 2};
+    int r = MBROWS2;
+    for (int lv : levels) {
+        long items = 0;
+        for (int k = 0; k < B->capacity; ++k) {
+            if (!in_list(B, k, LIST_PAIR)) continue;
+            const StepArgs& a = B->slot[k].a;
+            items += (long)a.p_nsx * ((a.y1 - a.y0 + lv - 1) / lv);
+        }
+        if (items >= ((lv > B->prows) ? need + need / 4 : need)) {
+            r = lv;
+            break;
+        }
+    }
+    if (r == B->prows) return MRTFD_OK;
+    B->prows = r;
+    int k0 = B->capacity, k1 = -1;
+    for (int k = 0; k < B->capacity; ++k) {
+        if (!B->used[k]) continue;
+        k0 = std::min(k0, k);
+        k1 = k;
+        if (B->shape[k] == MARCH) set_pair_rows(B->slot[k].a, r);
+    }
+    if (k1 >= k0)
+        HIPCHK(hipMemcpyAsync(B->d_slot + k0, &B->slot[k0], (size_t)(k1 - k0 + 1) * sizeof(BatchSlot),
+                              hipMemcpyHostToDevice, B->stream));
+    return MRTFD_OK;
+}
+
 // Rebuild the work lists over slots that still step.
 int rebuild_lists(mrtfd_batch_s* B)
 {
     int rc = fit_march_rows(B);
     if (rc) return rc;
-    std::vector<int> host(NLIST * (B->capacity + 1) + NLIST * B->capacity + B->capacity, 0);
+    rc = fit_pair_rows(B);
+    if (rc) return rc;
+    const size_t base = NLIST * (B->capacity + 1) + NLIST * B->capacity + B->capacity;
+    std::vector<int> host(base + pair_region_ints(B->capacity), 0);
     B->nwall = 0;
     for (int s = 0; s < NLIST; ++s) {
+        if (s == LIST_PAIR) continue;
         int n = 0, acc = 0;
         int* pre = host.data() + s * (B->capacity + 1);
         int* lst = host.data() + NLIST * (B->capacity + 1) + s * B->capacity;
@@ -285,7 +503,44 @@ int rebuild_lists(mrtfd_batch_s* B)
         }
         pre[n] = acc;
         B->nlist[s] = n;
-        if (s == LIST_PAIR) B->pair_items = acc;
+    }
+    // The two-step list, ordered so that the persistent pairs' totals even
+    // out: each slot's bands of the full height as one run and its shorter
+    // last band as another, the runs sorted by band height, tallest first
+    // (stable, so a slot's runs keep slot order among equals).  With the
+    // snake order in which k_march2_batch deals the items out, the pairs'
+    // totals differ by little more than the shortest items.  (Items dealt
+    // out in slot order, by a stride, left the most loaded pair about 16 %
+    // above the mean on the 512-instance Riemann mix, by a count of barrier
+    // iterations per item.)
+    {
+        struct Run {
+            int k, band0, nbands, height;
+        };
+        std::vector<Run> runs;
+        for (int k = 0; k < B->capacity; ++k) {
+            if (!in_list(B, k, LIST_PAIR)) continue;
+            const StepArgs& a = B->slot[k].a;
+            const int ey = a.y1 - a.y0, nfull = ey / a.p_rows, rest = ey - nfull * a.p_rows;
+            if (nfull > 0) runs.push_back({k, 0, nfull, a.p_rows});
+            if (rest > 0) runs.push_back({k, nfull, 1, rest});
+        }
+        std::stable_sort(runs.begin(), runs.end(), [](const Run& x, const Run& y) { return x.height > y.height; });
+        int* pre = host.data() + base;
+        int* lst = pre + 2 * B->capacity + 1;
+        int* bnd = lst + 2 * B->capacity;
+        long acc = 0;
+        int n = 0;
+        for (const Run& r : runs) {
+            pre[n] = (int)acc;
+            lst[n] = r.k;
+            bnd[n] = r.band0;
+            acc += (long)B->slot[r.k].a.p_nsx * r.nbands;
+            ++n;
+        }
+        pre[n] = (int)acc;
+        B->nlist[LIST_PAIR] = n;
+        B->pair_items = acc;
     }
     // slots whose walls a refill launch rewrites after each step: walls in
     // the tile classes, and walls along x (the strip kernels refill walls
@@ -314,8 +569,8 @@ int launch_list(mrtfd_batch_s* B, int s, long items, long L, hipStream_t st)
         // persistent pairs, a multiple of 8 blocks for the XCD-aware numbering
         long blocks = std::min<long>(items, B->pair_blocks);
         blocks = (blocks + 7) / 8 * 8;
-        hipLaunchKernelGGL((k_march2_batch<LIM, T>), dim3((int)blocks), dim3(2 * MW), 0, st, B->d_slot, pre,
-                           lst, n, L, B->R);
+        hipLaunchKernelGGL((k_march2_batch<LIM, T>), dim3((int)blocks), dim3(2 * MW), 0, st, B->d_slot,
+                           pair_prefix_dev(B), pair_list_dev(B), pair_band_dev(B), n, L, B->R);
         HIPCHK(hipGetLastError());
         return MRTFD_OK;
     }
@@ -573,12 +828,14 @@ int mrtfd_batch_create(int capacity, int precision, int limiter, void* hip_strea
     B->rstop.assign(capacity, LONG_MAX);
     B->per_launch = 2;
     B->mrows = MBROWS;
+    B->prows = MBROWS2;
     B->fit_rows = true;
     for (int s = 0; s < NSHAPE; ++s) {
         B->cost[s] = DEFAULT_COST[s];
         B->launch_us[s] = 10.0;
     }
-    const size_t lists = (size_t)(NLIST * (capacity + 1) + NLIST * capacity + capacity) * sizeof(int);
+    const size_t lists = ((size_t)(NLIST * (capacity + 1) + NLIST * capacity + capacity) + pair_region_ints(capacity)) *
+                         sizeof(int);
     if (hipMalloc(&B->d_slot, capacity * sizeof(BatchSlot)) != hipSuccess ||
         hipMalloc(&B->d_blocks, capacity * sizeof(Blocks)) != hipSuccess ||
         hipMalloc(&B->d_flags, capacity * sizeof(int)) != hipSuccess || hipMalloc(&B->d_lists, lists) != hipSuccess ||

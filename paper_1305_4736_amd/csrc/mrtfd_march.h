@@ -1085,144 +1085,3 @@ inline void set_march(StepArgs& a, long capacity_waves, double frac)
 }
 
 }  // namespace
-
-namespace {
-
-// Rows per band of a batched instance: short bands balance the static
-// assignment of items to wavefronts over instances of mixed sizes (8-12
-// rows measured best on a 512-instance mix; 32 rows cost 19 % more).
-#ifndef MARCH_BROWS
-#define MARCH_BROWS 12
-#endif
-constexpr int MBROWS = MARCH_BROWS;
-
-// Band layout of a batched instance: bands of at most MBROWS rows.
-inline void set_march_rows(StepArgs& a, int rows)
-{
-    const int ex = a.x1 - a.x0, ey = a.y1 - a.y0;
-    a.m_nsx = (ex + MOUT - 1) / MOUT;
-    a.m_rows = std::max(1, std::min(rows, ey));
-    a.m_nby = (ey + a.m_rows - 1) / a.m_rows;
-    a.m_per_xcd = 0;
-}
-
-// Batched form: persistent wavefronts stride over the (band, strip) items
-// of the listed slots, numbered slot after slot (prefix[k] = first item of
-// list[k]); wavefront g of the launch takes items g, g + G, ... where the
-// wavefronts of each XCD are numbered contiguously (the grid is a multiple
-// of 8 blocks).  The step and round counters L and R decide each slot's
-// current buffer and whether it still steps, as in the tile form.
-template <int LIM, typename T>
-__global__ void __launch_bounds__(MW * MWPB) k_march_batch(const BatchSlot* __restrict__ slots,
-                                                          const int* __restrict__ prefix,
-                                                          const int* __restrict__ list, int nlist, long L, long R)
-{
-    convect_mode();
-    const MRTFD_CONSTANT BatchSlot* cs = (const MRTFD_CONSTANT BatchSlot*)slots;
-    const MRTFD_CONSTANT int* cpre = (const MRTFD_CONSTANT int*)prefix;
-    const MRTFD_CONSTANT int* clist = (const MRTFD_CONSTANT int*)list;
-    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / MW)), lane = threadIdx.x % MW;
-    const int nb = gridDim.x, bid = blockIdx.x;
-    const int g = ((bid & 7) * (nb >> 3) + (bid >> 3)) * MWPB + w;
-    const int G = nb * MWPB;
-    const int nitems = cpre[nlist];
-    for (int item = g; item < nitems; item += G) {
-        int lo = 0, hi = nlist;
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (cpre[mid] <= item) lo = mid;
-            else hi = mid;
-        }
-        const MRTFD_CONSTANT BatchSlot& sl = cs[clist[lo]];
-        if (L >= sl.stop) continue;
-        CArgs& a = sl.a;
-        const int par = (int)(((sl.pair ? R : L) - sl.pstart) & 1);
-        const T* fin = (const T*)sl.buf[par];
-        T* fout = (T*)sl.buf[par ^ 1];
-        const int r = item - cpre[lo];
-        const int band = r / a.m_nsx, strip = r - band * a.m_nsx;
-        const int x = a.x0 + strip * MOUT - 2 + lane;
-        const bool out = lane >= 2 && lane < MW - 2 && x < a.x1;
-        const int yb = a.y0 + band * a.m_rows, ye = min(yb + a.m_rows, a.y1);
-        const unsigned bytes = (unsigned)(a.elems * (long)sizeof(T));
-        if (MARCH_ALTERNATE && (band & 1)) {
-            Marcher<LIM, T, -1> mr(&a, fin, fout, bytes, x, out);
-            mr.walk(yb, ye);
-            mr.refill_walls(yb, ye);
-        } else {
-            Marcher<LIM, T, 1> mr(&a, fin, fout, bytes, x, out);
-            mr.walk(yb, ye);
-            mr.refill_walls(yb, ye);
-        }
-    }
-}
-
-}  // namespace
-
-namespace {
-
-// Rows per pair band of a batched instance, and the fewest rows an instance
-// needs to take two steps per launch in the batch (measured on the
-// 512-instance Riemann mix: 32 / 8 beat bands of 16, 24, 48 and 64 rows and
-// minimums of 1, 4, 16 and 32 by 1-7 %).
-#ifndef MARCH2_BROWS
-#define MARCH2_BROWS 32
-#endif
-#ifndef MARCH2_BATCH_MIN_ROWS
-#define MARCH2_BATCH_MIN_ROWS 8
-#endif
-constexpr int MBROWS2 = MARCH2_BROWS;
-
-// Pair-band layout of a batched instance: bands of at most MBROWS2 rows.
-inline void set_pair_rows(StepArgs& a, int rows)
-{
-    const int ex = a.x1 - a.x0, ey = a.y1 - a.y0;
-    a.p_nsx = (ex + POUT - 1) / POUT;
-    a.p_rows = std::max(1, std::min(rows, ey));
-    a.p_nby = (ey + a.p_rows - 1) / a.p_rows;
-    a.p_per_xcd = 0;
-}
-
-// Batched two-step form: persistent blocks (one pair each) stride over the
-// (band, strip) items of the listed pair slots, XCD-aware as in
-// k_march_batch; every listed slot has two steps left (the caller's rule),
-// and its current buffer is the parity of R.  Both wavefronts of a block take
-// the same items, so they pass the same number of barriers.
-template <int LIM, typename T>
-__global__ void __launch_bounds__(2 * MW, MARCH2_MINW) k_march2_batch(const BatchSlot* __restrict__ slots,
-                                                                  const int* __restrict__ prefix,
-                                                                  const int* __restrict__ list, int nlist, long L,
-                                                                  long R)
-{
-    __shared__ PairRing<T> ring;
-    convect_mode();
-    const MRTFD_CONSTANT BatchSlot* cs = (const MRTFD_CONSTANT BatchSlot*)slots;
-    const MRTFD_CONSTANT int* cpre = (const MRTFD_CONSTANT int*)prefix;
-    const MRTFD_CONSTANT int* clist = (const MRTFD_CONSTANT int*)list;
-    const int role = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / MW)), lane = threadIdx.x % MW;
-    const int nb = gridDim.x, bid = blockIdx.x;
-    const int g = (bid & 7) * (nb >> 3) + (bid >> 3);
-    const int nitems = cpre[nlist];
-    for (int item = g; item < nitems; item += nb) {
-        int lo = 0, hi = nlist;
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (cpre[mid] <= item) lo = mid;
-            else hi = mid;
-        }
-        const MRTFD_CONSTANT BatchSlot& sl = cs[clist[lo]];
-        if (L + 1 >= sl.stop) continue;      // (not listed by the caller) both wavefronts skip
-        CArgs& a = sl.a;
-        const int par = (int)((R - sl.pstart) & 1);
-        const T* fin = (const T*)sl.buf[par];
-        T* fout = (T*)sl.buf[par ^ 1];
-        const int r = item - cpre[lo];
-        const int band = r / a.p_nsx, strip = r - band * a.p_nsx;
-        const int x = a.x0 + strip * POUT - 4 + lane;
-        const int yb = a.y0 + band * a.p_rows, ye = min(yb + a.p_rows, a.y1);
-        const unsigned bytes = (unsigned)(a.elems * (long)sizeof(T));
-        pair_walk<LIM, T, 1>(role, a, fin, fout, bytes, x, lane, yb, ye, &ring);
-    }
-}
-
-}  // namespace
