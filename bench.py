@@ -483,6 +483,27 @@ def summarize_profile(fetch_dir, write_dir, sq_dir, out_path):
     return out
 
 
+def summarize_counters(dirs):
+    """Mean per dispatch of every counter in rocprofv3 --pmc CSV output
+    directories, for each step kernel of PROFILE_KERNELS (counters summed
+    over a dispatch's rows), with the number of dispatches."""
+    out = {}
+    for d in dirs:
+        per = {}
+        for disp, name, cname, val in _counter_rows(d):
+            inst = next((i for i in PROFILE_KERNELS.values() if i in name), None)
+            if inst is None:
+                continue
+            per.setdefault(inst, {}).setdefault(cname, {}).setdefault(disp, 0.0)
+            per[inst][cname][disp] += val
+        for inst, cs in per.items():
+            o = out.setdefault(inst, {})
+            for cname, byd in cs.items():
+                o[cname] = sum(byd.values()) / len(byd)
+                o["dispatches"] = len(byd)
+    return out
+
+
 def summarize_trace(trace_dir, out_path, command, timed=(2, 12), kernel="k_march2<0, double>"):
     """Markdown summary of a rocprofv3 --kernel-trace --stats CSV run of the
     benchmark: the per-kernel statistics, and the durations of the headline
@@ -566,6 +587,9 @@ def main():
     ap.add_argument("--summarize-profile", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "SQ_DIR"),
                     help="write the counter summary of three rocprofv3 --pmc runs of the profile command "
                          "to profiles/ and exit (no GPU)")
+    ap.add_argument("--summarize-counters", nargs="+", metavar="PMC_DIR",
+                    help="print the mean per dispatch of every counter of rocprofv3 --pmc runs for the step "
+                         "kernels and exit (no GPU)")
     ap.add_argument("--summarize-trace", nargs=2, metavar=("TRACE_DIR", "OUT_MD"),
                     help="write the markdown summary of a rocprofv3 kernel trace of this benchmark and exit")
     ap.add_argument("--trace-command", default="rocprofv3 --kernel-trace --stats --output-format csv -d TRACE_DIR "
@@ -573,6 +597,9 @@ def main():
     args = ap.parse_args()
     if args.summarize_trace:
         print(summarize_trace(args.summarize_trace[0], args.summarize_trace[1], args.trace_command))
+        return
+    if args.summarize_counters:
+        print(json.dumps(summarize_counters(args.summarize_counters), indent=1))
         return
     if args.summarize_profile:
         out = summarize_profile(*args.summarize_profile, TRAFFIC_FILE)
