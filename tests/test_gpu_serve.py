@@ -63,3 +63,38 @@ def test_served_results_equal_alone_and_oracle(lib, orc, policy):
         if i % 3 == 0:
             fo = orc.run(p, case["rho"], case["ux"], case["uy"], case["T"], spec["nsteps"])
             assert_parity(served, orc.macros(p, fo), TOL[p["precision"]], 1.4, spec["name"])
+
+
+def test_failed_request_is_unphysical_for_the_oracle_too(lib, orc):
+    """The request the overloaded served streams report as failed, request
+    2041 of the 60-s stream at 200 requests/s (a quadrant problem on
+    135 x 175 in FP64 storage, 2969 steps; the stream's specs do not depend
+    on its rate), fails in the scheme, not in the GPU path: run alone, the
+    GPU state and the oracle's agree at the FP64 bar after 900 steps, both
+    physical; within the next 50 steps the oracle's temperature goes
+    negative at some node (from step 917 to 944, then positive again) and
+    the GPU flags the run."""
+    mrtfd, _ = lib
+    spec = W.serve_stream(rate=200.0, duration=60.0)[2041][1]
+    assert (spec["kind"], spec["params"]["nx"], spec["params"]["ny"]) == ("quadrant", 135, 175)
+    case = W.spec_case(spec)
+    p = dict(case["params"], precision="fp64")
+    print("[serve] request 2041 alone: GPU and oracle to step 900, then 50 more", flush=True)
+    with mrtfd.Solver(p) as s:
+        s.init(case["rho"], case["ux"], case["uy"], case["T"])
+        s.step(900)
+        s.sync()                                  # nothing flagged yet
+        m900 = s.macros()
+        s.step(50)
+        with pytest.raises(mrtfd.NonFiniteError):
+            s.sync()
+    fo = orc.run(p, case["rho"], case["ux"], case["uy"], case["T"], 900)
+    o900 = orc.macros(p, fo)
+    assert min(np.min(m900[3]), np.min(o900[3])) > 0.0
+    errs = assert_parity(m900, o900, TOL["fp64"], 1.4, "request 2041 at step 900")
+    tmin = []
+    for _ in range(50):
+        fo = orc.advance(p, fo, 1)
+        tmin.append(float(np.min(orc.macros(p, fo)[3])))
+    print(f"[serve] request 2041 at step 900: {errs}; oracle T min over steps 901-950: {min(tmin):.3e}", flush=True)
+    assert min(tmin) <= 0.0
