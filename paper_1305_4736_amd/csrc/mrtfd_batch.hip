@@ -14,7 +14,8 @@
 // columns x bands of up to 12 rows per wavefront), and LDS tiles of 256
 // threads: 32 x 8, 64 x 4, 128 x 2, and 256 x 1 rows for one-row instances.
 // Strip slots without walls along x and with at least 8 rows take two
-// steps per launch (k_march2_batch, bands of up to 32 rows) in two-step
+// steps per launch (k_march2_batch, bands of 32 to 160 rows fitted to the
+// load, items in a balanced order) in two-step
 // rounds, which the batch runs while their work fills the device; the
 // other slots, and such slots with one step left, then take one-step
 // launches.
