@@ -364,6 +364,7 @@ def run_batched(steps, warmup, log, n=512):
         nonfinite = 0
     except mrtfd.NonFiniteError as e:
         nonfinite = int((e.flags != 0).sum())
+    pair_rows = b.pair_rows()
     b.close()
     value = nodes * steps / (ms * 1e-3)
     log(f"[bench] batched {n} instances, {nodes} nodes: {ms / steps:.4f} ms/step, {value:.4e} node-updates/s")
@@ -373,7 +374,7 @@ def run_batched(steps, warmup, log, n=512):
             "screen": {"T_ratio_max": W.SCREEN[0], "p_ratio_max": W.SCREEN[1], "mach_max": W.SCREEN[2]},
             "screen_redraws": redraws, "nonfinite_instances": nonfinite,
             "autotune_us_per_unit": dict(zip(names, map(float, costs))),
-            "shape_classes": shapes}
+            "shape_classes": shapes, "pair_band_rows": pair_rows}
 
 
 def run_served(rate, seconds, log, drain, label, steps_per_tick=50, capacity=4096, cap_bytes=None,

@@ -290,6 +290,14 @@ int mrtfd_batch_remaining(mrtfd_batch_t b, int slot, long* remaining);
  * for NULL arguments. */
 int mrtfd_batch_rounds(mrtfd_batch_t b, long* one_step, long* two_step);
 
+/* Diagnostics: the band height (rows) of the batch's two-step launches as
+ * last fitted to the load: the tallest of 160, 128, 96, 80, 64, 48 and 32
+ * rows that gives every resident pair of the two-step kernel eight work
+ * items (1.25 times that to grow), refitted whenever the work lists change.
+ * The height changes no result, only the launch shape.  MRTFD_EINVAL for
+ * NULL arguments. */
+int mrtfd_batch_pair_rows(mrtfd_batch_t b, int* rows);
+
 /* Per-slot outputs and checkpoint, as the single-instance calls. */
 int mrtfd_batch_macros(mrtfd_batch_t b, int slot, double* rho, double* ux, double* uy, double* T,
                        int on_device);

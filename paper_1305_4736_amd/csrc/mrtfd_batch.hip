@@ -1063,6 +1063,13 @@ int mrtfd_batch_rounds(mrtfd_batch_t B, long* one_step, long* two_step)
     return MRTFD_OK;
 }
 
+int mrtfd_batch_pair_rows(mrtfd_batch_t B, int* rows)
+{
+    if (!B || !rows) return fail(MRTFD_EINVAL, "NULL argument");
+    *rows = B->prows;
+    return MRTFD_OK;
+}
+
 int mrtfd_batch_remaining(mrtfd_batch_t B, int k, long* remaining)
 {
     int rc = check_slot(B, k);

@@ -368,6 +368,7 @@ _lib.mrtfd_batch_steps_done.argtypes = [_B, ctypes.c_int]
 _lib.mrtfd_batch_steps_done.restype = ctypes.c_long
 _lib.mrtfd_batch_remaining.argtypes = [_B, ctypes.c_int, ctypes.POINTER(ctypes.c_long)]
 _lib.mrtfd_batch_rounds.argtypes = [_B, ctypes.POINTER(ctypes.c_long), ctypes.POINTER(ctypes.c_long)]
+_lib.mrtfd_batch_pair_rows.argtypes = [_B, ctypes.POINTER(ctypes.c_int)]
 _lib.mrtfd_batch_macros.argtypes = [_B, ctypes.c_int, _vp, _vp, _vp, _vp, ctypes.c_int]
 _lib.mrtfd_batch_get_f.argtypes = [_B, ctypes.c_int, _vp, ctypes.c_int]
 _lib.mrtfd_batch_set_f.argtypes = [_B, ctypes.c_int, _vp, ctypes.c_int]
@@ -469,6 +470,13 @@ class Batch:
         one, two = ctypes.c_long(0), ctypes.c_long(0)
         _check(_lib.mrtfd_batch_rounds(self._b, ctypes.byref(one), ctypes.byref(two)))
         return int(one.value), int(two.value)
+
+    def pair_rows(self) -> int:
+        """Band height of the two-step launches as last fitted to the load
+        (diagnostics)."""
+        rows = ctypes.c_int(0)
+        _check(_lib.mrtfd_batch_pair_rows(self._b, ctypes.byref(rows)))
+        return int(rows.value)
 
     def macros(self, slot: int, out=None):
         shp = self._shapes[slot]

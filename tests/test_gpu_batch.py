@@ -363,3 +363,44 @@ def test_full_riemann_batch_as_benchmarked(lib, orc):
         mo = orc.macros(p64, orc.run(p64, c["rho"], c["ux"], c["uy"], c["T"], n))
         gamma = (c["params"]["b"] + 2.0) / c["params"]["b"]
         assert_parity(mac[k], mo, TOL["fp32"], gamma, f"{c['name']} {c['params']['nx']}x{c['params']['ny']}")
+
+
+def test_fitted_pair_bands_match_alone(lib):
+    # Seven 4096 x 1024 instances give the two-step launches enough items
+    # for the fitted band height to grow to 48 rows (1628 items each at
+    # 48 rows, 1184 at 64, against eight per resident pair and 1.25 times
+    # that to grow); slots with walls along y whose last 48-row band is 1,
+    # 2 and 47 rows tall, next to the wall or not, and a ragged periodic
+    # one take their bands in the balanced order beside them.  Every such
+    # slot ends bitwise equal to its run alone, one step per launch.
+    big = [W.random_smooth(4096, 1024, seed=600 + k, bcs=[E, O, P, P], jumps=True, precision="fp32")
+           for k in range(7)]
+    small = [W.random_smooth(130, 49, seed=610, bcs=[P, P, WL, WH], jumps=True, precision="fp32"),
+             W.random_smooth(70, 50, seed=611, bcs=[E, O, WL, O], jumps=True, precision="fp32"),
+             W.random_smooth(200, 95, seed=612, bcs=[O, O, O, WH], jumps=True, precision="fp32"),
+             W.random_smooth(333, 97, seed=613, bcs=[P, P, P, P], jumps=True, precision="fp32")]
+    n = 6
+    print("[batch] fitted pair bands: 7 x 4096 x 1024 and 4 small slots, 6 steps", flush=True)
+    with lib.Batch(len(big) + len(small), precision="fp32") as b:
+        slots = add_all(b, big + small)
+        b.step(n)
+        b.status()
+        rows = b.pair_rows()
+        one, two = b.rounds()
+        got = [b.get_f(s) for s in slots[len(big):]]
+        big0 = b.macros(slots[0])
+    assert rows == 48 and two == n // 2, (rows, one, two)
+    for c, g in zip(small, got):
+        with lib.Solver(c["params"]) as single:
+            single.steps_per_launch = 1
+            single.init(c["rho"], c["ux"], c["uy"], c["T"])
+            single.step(n)
+            assert np.array_equal(single.get_f(), g), c["name"]
+    c = big[0]
+    with lib.Solver(c["params"]) as single:
+        single.steps_per_launch = 1
+        single.init(c["rho"], c["ux"], c["uy"], c["T"])
+        single.step(n)
+        single.sync()
+        alone = single.macros()
+    assert all(np.array_equal(a, m) for a, m in zip(alone, big0))
