@@ -474,10 +474,24 @@ def summarize_profile(fetch_dir, write_dir, sq_dir, out_path):
                         "hbm_over_algorithmic": round((fb + wb) / alg, 4) if alg else None,
                         "valu_insts_per_launch": v, "waves_per_launch": wv, "valu_insts_per_wave": v / wv if wv else None,
                         "grbm_gui_active_per_launch": g}
+    # A witness of the calibration: the FP64 initialisation of the same
+    # grid reads four FP64 fields (32 B per node) and writes 16 FP64
+    # populations (128 B per node), each byte once, in plain streaming
+    # accesses; its scaled counters should read those bytes.
+    fi, ni = match(fetch, "k_init<double>")
+    wi, _ = match(write, "k_init<double>")
+    witness = None
+    if fi is not None and wi is not None:
+        witness = {"kernel": "k_init<double>", "dispatches": ni,
+                   "fetch_bytes": round(1024 * fi * fetch_factor), "write_bytes": round(1024 * wi * write_factor),
+                   "expected_read_bytes": 32 * nodes, "expected_write_bytes": 128 * nodes,
+                   "fetch_over_expected": round(1024 * fi * fetch_factor / (32 * nodes), 4),
+                   "write_over_expected": round(1024 * wi * write_factor / (128 * nodes), 4)}
     out = {"workload": "shock_interface_4096x1024 (single-grid kernels), riemann_batch_512 (batched)",
            "kernel_hash": kernel_hash(),
            "command": PROFILE_COMMAND, "passes": ["FETCH_SIZE", "WRITE_SIZE", "SQ_INSTS_VALU SQ_WAVES GRBM_GUI_ACTIVE"],
            "copy_calibration": {"bytes": int(gib), "fetch_factor": fetch_factor, "write_factor": write_factor},
+           "calibration_witness": witness,
            "kernels": kernels}
     with open(out_path, "w") as fh:
         json.dump(out, fh, indent=1)
