@@ -72,3 +72,36 @@ def test_macro_errors_use_the_flow_speed():
     still = (ref[0], np.zeros((2, 3)), ref[2], ref[3])
     e = bench.macro_errors((ref[0], still[1] + 1e-6, ref[2], ref[3]), still, 1.4)
     assert abs(e["ux"][1] - 1e-6 / 1.4 ** 0.5) < 1e-12
+
+
+def test_fetch_bytes_are_scaled_by_the_initialisation_kernel(tmp_path):
+    """FETCH_SIZE is scaled so that the FP64 initialisation of the
+    4096 x 1024 grid reads its 32 B per node; WRITE_SIZE by the plain
+    copy's writes.  Synthetic counter files: the copy reads 1/2.667 of its
+    bytes on FETCH_SIZE and the initialisation 1/2 of its own."""
+    import csv
+    import bench
+
+    def write(d, rows):
+        os.makedirs(os.path.join(d, "x"))
+        with open(os.path.join(d, "x", "pmc_counter_collection.csv"), "w", newline="") as fh:
+            w = csv.writer(fh)
+            w.writerow(["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+            w.writerows(rows)
+
+    gib, nodes = 1 << 30, 4096 * 1024
+    pair = "void (anonymous namespace)::k_march2<0, double>(double const*, double*)"
+    init = "void (anonymous namespace)::k_init<double>(double*)"
+    write(tmp_path / "f", [(1, "copy", "FETCH_SIZE", gib / 1024 / 2.667), (2, init, "FETCH_SIZE", 32 * nodes / 1024 / 2),
+                           (3, pair, "FETCH_SIZE", 300000.0)])
+    write(tmp_path / "w", [(1, "copy", "WRITE_SIZE", gib / 1024), (2, init, "WRITE_SIZE", 128 * nodes / 1024),
+                           (3, pair, "WRITE_SIZE", 500000.0)])
+    write(tmp_path / "s", [(3, pair, "SQ_INSTS_VALU", 1e8), (3, pair, "SQ_WAVES", 1936.0),
+                           (3, pair, "GRBM_GUI_ACTIVE", 4e6)])
+    out = bench.summarize_profile(tmp_path / "f", tmp_path / "w", tmp_path / "s", tmp_path / "o.json")
+    assert abs(out["fetch_calibration"]["fetch_factor"] - 2.0) < 1e-12
+    assert abs(out["copy_calibration"]["fetch_factor"] - 2.667) < 1e-9
+    assert out["fetch_calibration"]["write_over_expected"] == 1.0
+    k = out["kernels"]["k_march2/fp64"]
+    assert k["fetch_bytes_per_launch"] == round(300000.0 * 1024 * 2.0)
+    assert k["write_bytes_per_launch"] == round(500000.0 * 1024)
