@@ -9,13 +9,16 @@ whole grid; value = interior node-updates per second over the timed steps,
 inputs resident in HBM.
 
 Printed: ONE JSON line with the contract fields plus
-  roofline     -- the step kernel's algorithmic HBM bytes per launch
-                  (16 reads + 16 writes of f per node-update; an FP64 launch
-                  takes two steps, i.e. two node-updates per node) over its
-                  average launch time, measured with HIP events on the
-                  library's stream inside the timed region; traffic (the HBM
-                  bytes the launch actually moves) from the committed
-                  rocprofv3 counter summary when it matches the current kernel
+  roofline     -- the step kernel against the nearer of two roofs: VALU
+                  issue (SQ_INSTS_VALU per launch) and HBM (the bytes the
+                  launch moves, FETCH_SIZE + WRITE_SIZE scaled by kernels of
+                  known traffic), both from the committed rocprofv3 counter
+                  summary when it matches the current kernel code, over the
+                  average launch time measured with HIP events on the
+                  library's stream inside the timed region; beside them the
+                  algorithmic rate (16 reads + 16 writes of f per
+                  node-update; a two-step launch counts two node-updates per
+                  node) as hbm_effective
   cpu_baseline -- the FP64 oracle on the host, on a bounded sample of the
                   same workload (a few full-grid steps)
   fp64_one_step_per_launch -- the FP64 workload with one step per launch
