@@ -269,7 +269,7 @@ int mrtfd_batch_set_steps(mrtfd_batch_t b, int slot, long nsteps);
 int mrtfd_batch_step(mrtfd_batch_t b, long nsteps);
 
 /* Steps per launch of the batch's two-step rounds: with k = 2 (default),
- * slots in the strip class without walls along x and with at least 8 rows
+ * slots in the strip class without walls along x and with at least 4 rows
  * take two steps per launch (the second step reading the first's rows from
  * on-chip memory) in rounds where their work fills the device (a smaller
  * batch is faster one step at a time); other slots, and such slots with one

@@ -13,7 +13,7 @@
 // Shape classes: the row-marching strips of mrtfd_march.h (60 output
 // columns x bands of up to 12 rows per wavefront), and LDS tiles of 256
 // threads: 32 x 8, 64 x 4, 128 x 2, and 256 x 1 rows for one-row instances.
-// Strip slots without walls along x and with at least 8 rows take two
+// Strip slots without walls along x and with at least 4 rows take two
 // steps per launch (k_march2_batch, bands of 32 to 160 rows fitted to the
 // load, items in a balanced order) in two-step
 // rounds, which the batch runs while their work fills the device; the
@@ -114,14 +114,17 @@ namespace {
 
 // Rows per pair band of a batched instance (the shortest of the heights
 // fit_pair_rows chooses from), and the fewest rows an instance needs to take
-// two steps per launch in the batch (with items dealt out in slot order, by
+// two steps per launch in the batch.  With items dealt out in slot order, by
 // a stride, 32 / 8 beat bands of 16, 24, 48 and 64 rows and minimums of 1,
-// 4, 16 and 32 by 1-7 % on the 512-instance Riemann mix).
+// 4, 16 and 32 by 1-7 % on the 512-instance Riemann mix; with the balanced
+// order and fitted heights a minimum of 4 rows is 3 % faster than 8 on the
+// same mix (0.784 against 0.808 ms per step, same box, three runs each; 2
+// rows 0.788).
 #ifndef MARCH2_BROWS
 #define MARCH2_BROWS 32
 #endif
 #ifndef MARCH2_BATCH_MIN_ROWS
-#define MARCH2_BATCH_MIN_ROWS 8
+#define MARCH2_BATCH_MIN_ROWS 4
 #endif
 constexpr int MBROWS2 = MARCH2_BROWS;
 
