@@ -105,3 +105,28 @@ def test_fetch_bytes_are_scaled_by_the_initialisation_kernel(tmp_path):
     k = out["kernels"]["k_march2/fp64"]
     assert k["fetch_bytes_per_launch"] == round(300000.0 * 1024 * 2.0)
     assert k["write_bytes_per_launch"] == round(500000.0 * 1024)
+
+
+def test_summarize_counters_means_per_dispatch(tmp_path):
+    """--summarize-counters: each counter summed over a dispatch's rows,
+    then averaged over the dispatches of each step kernel; other kernels
+    (a copy) are left out."""
+    import csv
+    import bench
+
+    d = tmp_path / "s"
+    os.makedirs(d / "x")
+    pair = "void (anonymous namespace)::k_march2<0, double>(double const*, double*)"
+    one = "void (anonymous namespace)::k_march<0, double>(double const*, double*)"
+    with open(d / "x" / "pmc_counter_collection.csv", "w", newline="") as fh:
+        w = csv.writer(fh)
+        w.writerow(["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+        w.writerows([(1, pair, "SQ_WAVES", 1000.0), (1, pair, "SQ_WAVES", 936.0), (2, pair, "SQ_WAVES", 1936.0),
+                     (1, pair, "SQ_WAIT_ANY", 5.0), (2, pair, "SQ_WAIT_ANY", 7.0),
+                     (3, one, "SQ_WAVES", 992.0), (4, "copy", "SQ_WAVES", 64.0)])
+    out = bench.summarize_counters([d])
+    assert set(out) == {"k_march2<0, double>", "k_march<0, double>"}
+    assert out["k_march2<0, double>"]["SQ_WAVES"] == 1936.0
+    assert out["k_march2<0, double>"]["SQ_WAIT_ANY"] == 6.0
+    assert out["k_march2<0, double>"]["dispatches"] == 2
+    assert out["k_march<0, double>"]["SQ_WAVES"] == 992.0
