@@ -11,8 +11,8 @@ A sample of the Riemann instances is also checked against the oracle itself
 over their full 1000 steps (one row: the instances are uniform in y).
 
 Workloads: the 4096 x 1024 shock-interface problem for 2000 steps; all 512
-Riemann instances of the batch for 1000 steps; the first 24 requests of the
-served stream (quadrant problems and thermal Couette flows, 1107-4884
+Riemann instances of the batch for 1000 steps; the first 124 requests of
+the served stream (quadrant problems and thermal Couette flows, 342-5000
 steps); the 4 x 200 thermal Couette flow for 20 000 steps.
 """
 import numpy as np
@@ -115,7 +115,7 @@ def test_fp32_riemann_batch_1000_steps(lib, orc):
 
 
 def test_fp32_served_requests_full_length(lib):
-    reqs = W.serve_stream(rate=200.0, duration=60.0)[:24]
+    reqs = W.serve_stream(rate=200.0, duration=60.0)[:124]
     cases = [W.spec_case(spec) for _, spec in reqs]
     print(f"[fp32] first {len(cases)} served requests at their full lengths", flush=True)
     m64 = batch_solve(lib, cases, "fp64", lambda c: c["nsteps"])
